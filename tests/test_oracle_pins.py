@@ -1,0 +1,565 @@
+"""Pins of the FP64 CPU oracle against values the mathematics or the
+literature fix, independent of the oracle's own code paths.
+
+Each test names what it pins.  Closed forms are evaluated with mpmath at
+25+ digits; p-type integrals are taken as centre derivatives of the s-type
+closed forms ((1/2a) d/dA_x of exp(-a|r-A|^2) is x_A exp(-a|r-A|^2)), which
+is brute force independent of the Obara-Saika recurrences used by the oracle.
+"""
+import json
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2311_01135_amd import molgen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+BOHR = 0.52917721092
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Boys function: F_m(T) = gamma(m + 1/2, T) / (2 T^(m+1/2))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("T", [0.0, 1e-14, 1e-9, 1e-4, 0.3, 1.0, 5.0, 12.0, 29.99, 30.0, 30.01, 45.0, 120.0, 1e4])
+def test_boys_vs_incomplete_gamma(T):
+    mp.mp.dps = 30
+    F = O.boys(6, T)
+    for m in range(7):
+        if T == 0.0:
+            ref = mp.mpf(1) / (2 * m + 1)
+        else:
+            ref = mp.gammainc(m + mp.mpf(1) / 2, 0, T) / (2 * mp.mpf(T) ** (m + mp.mpf(1) / 2))
+        assert abs(F[m] - float(ref)) <= 2e-15 * max(1.0, float(ref)) + 1e-300, (m, T, F[m], ref)
+
+
+def test_boys_large_T_asymptote():
+    # F_m(T) -> (2m-1)!! / 2^(m+1) sqrt(pi / T^(2m+1)) for large T
+    T = 200.0
+    F = O.boys(4, T)
+    for m in range(5):
+        dfact = 1.0
+        for k in range(2 * m - 1, 0, -2):
+            dfact *= k
+        ref = dfact / 2 ** (m + 1) * math.sqrt(math.pi / T ** (2 * m + 1))
+        assert abs(F[m] / ref - 1) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# basis data
+# --------------------------------------------------------------------------
+def test_sto3g_zeta_scaling_spot_values():
+    """Universal zeta = 1 STO-3G expansions scaled by zeta^2 reproduce the
+    per-element exponents printed in the STO-3G literature (Hehre, Stewart,
+    Pople 1969, as tabulated per element)."""
+    m = O.Mol([8, 1, 1], np.array([[0, 0, 0], [0.9, 0, 0.3], [-0.9, 0, 0.3]]))
+    L, at, b0, a, c = m.shell(0)       # O 1s
+    assert L == 0 and abs(a[0] - 130.70932) < 2e-4
+    L, at, b0, a, c = m.shell(1)       # O 2s
+    assert abs(a[0] - 5.0331513) < 2e-6 and abs(a[1] - 1.1695961) < 2e-6 and abs(a[2] - 0.3803890) < 2e-6
+    L, at, b0, a, c = m.shell(3)       # H 1s
+    assert np.allclose(a, [3.42525091, 0.62391373, 0.16885540], rtol=0, atol=2e-7)
+
+
+def test_normalisation_diagonal_overlap():
+    Z, x = molgen.tree(2, 11, 0)
+    m = O.Mol(Z, x)
+    S, T, V = m.int1e()
+    assert np.allclose(np.diag(S), 1.0, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# closed-form primitive integrals (mpmath) and centre derivatives
+# --------------------------------------------------------------------------
+def _F0(T):
+    if T == 0:
+        return mp.mpf(1)
+    return mp.sqrt(mp.pi / T) * mp.erf(mp.sqrt(T)) / 2
+
+
+def _s_overlap(a, A, b, B):
+    p = a + b
+    R2 = sum((A[i] - B[i]) ** 2 for i in range(3))
+    return (mp.pi / p) ** 1.5 * mp.exp(-a * b / p * R2)
+
+
+def _s_kinetic(a, A, b, B):
+    p = a + b
+    mu = a * b / p
+    R2 = sum((A[i] - B[i]) ** 2 for i in range(3))
+    return mu * (3 - 2 * mu * R2) * (mp.pi / p) ** 1.5 * mp.exp(-mu * R2)
+
+
+def _s_nuclear(a, A, b, B, Cs, Zs):
+    p = a + b
+    R2 = sum((A[i] - B[i]) ** 2 for i in range(3))
+    P = [(a * A[i] + b * B[i]) / p for i in range(3)]
+    tot = 0
+    for C, Z in zip(Cs, Zs):
+        PC2 = sum((P[i] - C[i]) ** 2 for i in range(3))
+        tot += -Z * 2 * mp.pi / p * mp.exp(-a * b / p * R2) * _F0(p * PC2)
+    return tot
+
+
+def _s_eri(a, A, b, B, c, C, d, D):
+    p, q = a + b, c + d
+    Rab = sum((A[i] - B[i]) ** 2 for i in range(3))
+    Rcd = sum((C[i] - D[i]) ** 2 for i in range(3))
+    P = [(a * A[i] + b * B[i]) / p for i in range(3)]
+    Q = [(c * C[i] + d * D[i]) / q for i in range(3)]
+    PQ2 = sum((P[i] - Q[i]) ** 2 for i in range(3))
+    al = p * q / (p + q)
+    return (2 * mp.pi ** 2.5 / (p * q * mp.sqrt(p + q)) * mp.exp(-a * b / p * Rab)
+            * mp.exp(-c * d / q * Rcd) * _F0(al * PQ2))
+
+
+class _Basis:
+    """AO -> (exponents, coefficients, centre, Cartesian direction or -1) from the oracle."""
+
+    def __init__(self, m, Z, xyz):
+        self.R = np.asarray(xyz, dtype=float).reshape(-1, 3) / BOHR
+        self.Z = list(Z)
+        self.ao = []
+        for s in range(m.nshell):
+            L, at, b0, a, c = m.shell(s)
+            if L == 0:
+                self.ao.append((a.copy(), c.copy(), at, -1))
+            else:
+                for k in range(3):
+                    self.ao.append((a.copy(), c.copy(), at, k))
+
+
+def _contracted(basis, aos, prim_fn):
+    """sum over primitives of prod(c) * prod(1/(2a) for p) * d^n/dA^n prim_fn."""
+    tot = mp.mpf(0)
+    n = len(aos)
+    info = [basis.ao[i] for i in aos]
+
+    def rec(level, exps, coef, scale):
+        nonlocal tot
+        if level == n:
+            cen = [[mp.mpf(float(v)) for v in basis.R[inf[2]]] for inf in info]
+            dvars = [(k, inf[3]) for k, inf in enumerate(info) if inf[3] >= 0]
+
+            def f(*xs):
+                cc = [list(c) for c in cen]
+                for (k, d), xv in zip(dvars, xs):
+                    cc[k][d] = xv
+                return prim_fn(exps, cc)
+
+            if dvars:
+                x0 = [cen[k][d] for k, d in dvars]
+                val = mp.diff(f, x0, tuple(1 for _ in dvars))
+            else:
+                val = f()
+            tot += coef * scale * val
+            return
+        a, c, at, d = info[level]
+        for k in range(3):
+            ak = mp.mpf(float(a[k]))
+            rec(level + 1, exps + [ak], coef * mp.mpf(float(c[k])), scale * (1 / (2 * ak) if d >= 0 else 1))
+
+    rec(0, [], mp.mpf(1), mp.mpf(1))
+    return tot
+
+
+@pytest.fixture(scope="module")
+def water_mol():
+    Z, x = molgen.water(0)
+    return Z, x, O.Mol(Z, x)
+
+
+def test_one_electron_vs_closed_forms(water_mol):
+    mp.mp.dps = 30
+    Z, x, m = water_mol
+    S, T, V = m.int1e()
+    b = _Basis(m, Z, x)
+    Cs = [[mp.mpf(float(v)) for v in r] for r in b.R]
+    N = m.nbf
+    for i in range(N):
+        for j in range(i + 1):
+            s = _contracted(b, [i, j], lambda e, c: _s_overlap(e[0], c[0], e[1], c[1]))
+            t = _contracted(b, [i, j], lambda e, c: _s_kinetic(e[0], c[0], e[1], c[1]))
+            v = _contracted(b, [i, j], lambda e, c: _s_nuclear(e[0], c[0], e[1], c[1], Cs, b.Z))
+            assert abs(S[i, j] - float(s)) < 1e-12, (i, j)
+            assert abs(T[i, j] - float(t)) < 1e-11, (i, j)
+            assert abs(V[i, j] - float(v)) < 1e-11, (i, j)
+
+
+def test_eri_vs_closed_forms_sample(water_mol):
+    """(ss|ss) closed form, p-types by centre derivatives; all 6 classes."""
+    mp.mp.dps = 25
+    Z, x, m = water_mol
+    b = _Basis(m, Z, x)
+    # water AOs: 0 O1s, 1 O2s, 2-4 O2p, 5 H1s, 6 H1s
+    quartets = [(0, 0, 0, 0), (5, 6, 5, 6), (1, 5, 6, 0), (2, 0, 0, 0), (3, 5, 6, 6), (2, 2, 5, 5),
+                (4, 3, 1, 6), (2, 5, 3, 6), (4, 2, 3, 5), (2, 2, 2, 2), (3, 2, 4, 2), (4, 4, 3, 3)]
+    for (i, j, k, l) in quartets:
+        ref = _contracted(b, [i, j, k, l],
+                          lambda e, c: _s_eri(e[0], c[0], e[1], c[1], e[2], c[2], e[3], c[3]))
+        got = m.eri_one(i, j, k, l)
+        assert abs(got - float(ref)) < 1e-11, ((i, j, k, l), got, ref)
+
+
+def _pair(i, j):
+    return i * (i + 1) // 2 + j if i >= j else j * (j + 1) // 2 + i
+
+
+def _unpack(eri, N):
+    full = np.zeros((N, N, N, N))
+    for i in range(N):
+        for j in range(N):
+            for k in range(N):
+                for l in range(N):
+                    ij, kl = _pair(i, j), _pair(k, l)
+                    full[i, j, k, l] = eri[_pair(ij, kl)]
+    return full
+
+
+@pytest.fixture(scope="module")
+def small_tree():
+    Z, x = molgen.tree(1, 5, 3)       # one heavy atom + H: N <= 9
+    m = O.Mol(Z, x)
+    return Z, x, m, m.eri()
+
+
+def test_eri_packed_matches_single_evaluations(small_tree):
+    Z, x, m, eri = small_tree
+    N = m.nbf
+    rng = np.random.default_rng(0)
+    for _ in range(40):
+        i, j, k, l = rng.integers(0, N, 4)
+        assert abs(eri[_pair(_pair(i, j), _pair(k, l))] - m.eri_one(i, j, k, l)) < 1e-14
+
+
+def test_eri_supermatrix_psd_and_schwarz(small_tree):
+    Z, x, m, eri = small_tree
+    N = m.nbf
+    full = _unpack(eri, N)
+    M = full.reshape(N * N, N * N)
+    assert np.allclose(M, M.T, atol=0)
+    w = np.linalg.eigvalsh(M)
+    assert w.min() > -1e-12
+    d = np.einsum("ijij->ij", full)
+    lhs = np.abs(full)
+    rhs = np.sqrt(np.einsum("ij,kl->ijkl", d, d))
+    assert (lhs <= rhs + 1e-13).all()
+
+
+def test_eri_translation_invariance():
+    Z, x = molgen.water(3)
+    e1 = O.Mol(Z, x).eri()
+    e2 = O.Mol(Z, x + np.array([0.7, -1.3, 2.1])).eri()
+    assert np.abs(e1 - e2).max() < 1e-12
+
+
+def test_jk_packed_vs_dense_einsum(small_tree):
+    Z, x, m, eri = small_tree
+    N = m.nbf
+    full = _unpack(eri, N)
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((N, N))
+    P = A + A.T
+    J, K = m.jk(eri, P)
+    Jd = np.einsum("ijkl,kl->ij", full, P)
+    Kd = np.einsum("ikjl,kl->ij", full, P)
+    assert np.abs(J - Jd).max() < 1e-13
+    assert np.abs(K - Kd).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# grid
+# --------------------------------------------------------------------------
+def test_gauss_legendre_vs_numpy():
+    for n in (1, 2, 5, 12, 18):
+        x, w = O.gauss_legendre(n)
+        xr, wr = np.polynomial.legendre.leggauss(n)
+        o = np.argsort(x)
+        assert np.allclose(x[o], xr, atol=1e-15) and np.allclose(w[o], wr, atol=1e-14)
+
+
+def test_radial_rule_gaussian_moments():
+    r, w = O.radial(50)
+    # int_0^inf r^2 exp(-a r^2) dr = sqrt(pi)/(4 a^1.5)
+    for a in (0.2, 1.0, 5.0, 60.0):
+        ref = math.sqrt(math.pi) / (4 * a ** 1.5)
+        assert abs((w * np.exp(-a * r * r)).sum() / ref - 1) < 2e-6, a
+    assert (r > 0).all() and (w > 0).all()
+
+
+def _single_atom_grid():
+    # H^- (2 electrons) gives a one-atom molecule: Becke weights are exactly 1
+    m = O.Mol([1], np.zeros((1, 3)), charge=-1)
+    return m, m.grid(50, 12, 24)
+
+
+def test_angular_rule_exact_for_monomials():
+    m, g = _single_atom_grid()
+    xyz, w = g[:, :3], g[:, 3]
+    r = np.sqrt((xyz ** 2).sum(1))
+    u = xyz / r[:, None]
+    rr, wr = O.radial(50)
+    wrad = np.repeat(wr, 12 * 24)
+    wang = w / wrad
+    for (a, b, c) in [(0, 0, 0), (2, 0, 0), (0, 0, 2), (2, 2, 2), (4, 0, 6), (1, 1, 0), (0, 3, 1),
+                      (8, 6, 8), (10, 0, 12), (0, 22, 0), (23, 0, 0)]:
+        got = (wang * u[:, 0] ** a * u[:, 1] ** b * u[:, 2] ** c).sum() / (50)
+        if a % 2 or b % 2 or c % 2:
+            ref = 0.0
+        else:
+            ref = 2 * math.gamma((a + 1) / 2) * math.gamma((b + 1) / 2) * math.gamma((c + 1) / 2) / math.gamma((a + b + c + 3) / 2)
+        assert abs(got - ref) < 1e-12, (a, b, c, got, ref)
+
+
+def test_becke_partition_integrates_gaussians():
+    """A normalised Gaussian integrates to 1 over the molecular grid: the
+    fuzzy-cell weights sum to one at every point."""
+    Z, x = molgen.water(1)
+    m = O.Mol(Z, x)
+    g = m.grid()
+    R = np.asarray(x) / BOHR
+    for cen, a in [(R[0] + [0.3, -0.2, 0.1], 1.0), (R[1], 2.0), (0.5 * (R[1] + R[2]), 0.7)]:
+        d2 = ((g[:, :3] - cen) ** 2).sum(1)
+        val = (g[:, 3] * np.exp(-a * d2)).sum() / (math.pi / a) ** 1.5
+        assert abs(val - 1) < 1e-5, (cen, a, val)
+
+
+# --------------------------------------------------------------------------
+# functional
+# --------------------------------------------------------------------------
+RNG_RHO = np.array([1e-10, 1e-6, 1e-3, 0.02, 0.3, 1.0, 7.0, 150.0])
+
+
+def test_slater_is_dirac_exchange():
+    # e_x = rho * (-3/(4 pi)) k_F, k_F = (3 pi^2 rho)^(1/3)
+    e, vr, vs = O.functional(10, RNG_RHO, np.zeros_like(RNG_RHO))
+    kf = (3 * math.pi ** 2 * RNG_RHO) ** (1 / 3)
+    ref = RNG_RHO * (-3 / (4 * math.pi)) * kf
+    assert np.allclose(e, ref, rtol=1e-14, atol=0)
+    assert np.allclose(vr, 4 / 3 * ref / RNG_RHO, rtol=1e-14, atol=0)
+
+
+def test_b88_reduces_to_slater_without_gradient():
+    e, vr, vs = O.functional(11, RNG_RHO, np.zeros_like(RNG_RHO))
+    es, vrs, _ = O.functional(10, RNG_RHO, np.zeros_like(RNG_RHO))
+    assert np.allclose(e, es, rtol=1e-14, atol=0) and np.allclose(vr, vrs, rtol=1e-14, atol=0)
+
+
+def test_b88_large_gradient_asymptote():
+    """Becke's form: per spin, e -> -rho_s^(4/3) x / (6 ln 2x) + LDA as x -> inf."""
+    rho = np.array([1e-3])
+    rs = rho / 2
+    for x in (1e6, 1e8):
+        gs = x * rs ** (4 / 3)
+        sigma = (2 * gs) ** 2
+        e, _, _ = O.functional(11, rho, sigma)
+        es, _, _ = O.functional(10, rho, np.zeros(1))
+        got = (e - es) / 2
+        ref = -rs ** (4 / 3) * x / (6 * math.log(2 * x))
+        assert abs(got[0] / ref[0] - 1) < 0.05
+
+
+def test_vwn_high_density_log_coefficient():
+    """Paramagnetic correlation: eps_c = A ln rs + const + ... as rs -> 0 with
+    A = (1 - ln 2)/pi^2 (Gell-Mann & Brueckner)."""
+    A = (1 - math.log(2)) / math.pi ** 2
+    for xc in (12, 13):
+        rs = np.array([1e-6, 1e-7])
+        rho = 3 / (4 * math.pi * rs ** 3)
+        e, _, _ = O.functional(xc, rho, np.zeros(2))
+        eps = e / rho
+        slope = (eps[0] - eps[1]) / math.log(rs[0] / rs[1])
+        assert abs(slope / A - 1) < 1e-3, (xc, slope, A)
+
+
+def _sympy_b3lyp(vwn5=False):
+    import sympy as sp
+    rho, sigma = sp.symbols("rho sigma", positive=True)
+    pi = sp.pi
+    # Slater + B88 written per spin, closed shell rho_s = rho/2, |grad rho_s| = sqrt(sigma)/2
+    Cx = sp.Rational(3, 2) * (3 / (4 * pi)) ** sp.Rational(1, 3)
+    beta = sp.Rational(42, 10000)
+    rs_ = rho / 2
+    gs = sp.sqrt(sigma) / 2
+    x = gs / rs_ ** sp.Rational(4, 3)
+    b88 = 2 * (-rs_ ** sp.Rational(4, 3) * Cx - beta * rs_ ** sp.Rational(4, 3) * x ** 2 / (1 + 6 * beta * x * sp.asinh(x)))
+    slater = 2 * (-Cx * rs_ ** sp.Rational(4, 3))
+    # VWN paramagnetic
+    A = sp.Float("0.0310907", 30)
+    if vwn5:
+        b, c, x0 = sp.Float("3.72744", 30), sp.Float("12.9352", 30), sp.Float("-0.10498", 30)
+    else:
+        b, c, x0 = sp.Float("13.0720", 30), sp.Float("42.7198", 30), sp.Float("-0.409286", 30)
+    r_s = (3 / (4 * pi * rho)) ** sp.Rational(1, 3)
+    xx = sp.sqrt(r_s)
+    X = xx ** 2 + b * xx + c
+    X0 = x0 ** 2 + b * x0 + c
+    Q = sp.sqrt(4 * c - b ** 2)
+    eps = A * (sp.log(xx ** 2 / X) + 2 * b / Q * sp.atan(Q / (2 * xx + b))
+               - b * x0 / X0 * (sp.log((xx - x0) ** 2 / X) + 2 * (b + 2 * x0) / Q * sp.atan(Q / (2 * xx + b))))
+    vwn = rho * eps
+    # LYP, general spin-resolved gradient form (Miehlich, Savin, Stoll, Preuss 1989)
+    a_, b_, c_, d_ = (sp.Float(v, 30) for v in ("0.04918", "0.132", "0.2533", "0.349"))
+    ra, rb = rho / 2, rho / 2
+    ga2, gb2, g2 = sigma / 4, sigma / 4, sigma
+    CF = sp.Rational(3, 10) * (3 * pi ** 2) ** sp.Rational(2, 3)
+    t = rho ** sp.Rational(-1, 3)
+    om = sp.exp(-c_ * t) / (1 + d_ * t) * rho ** sp.Rational(-11, 3)
+    de = c_ * t + d_ * t / (1 + d_ * t)
+    lyp = (-a_ * 4 / (1 + d_ * t) * ra * rb / rho
+           - a_ * b_ * om * (ra * rb * (2 ** sp.Rational(11, 3) * CF * (ra ** sp.Rational(8, 3) + rb ** sp.Rational(8, 3))
+                                        + (sp.Rational(47, 18) - sp.Rational(7, 18) * de) * g2
+                                        - (sp.Rational(5, 2) - de / 18) * (ga2 + gb2)
+                                        - (de - 11) / 9 * (ra / rho * ga2 + rb / rho * gb2))
+                             - sp.Rational(2, 3) * rho ** 2 * g2
+                             + (sp.Rational(2, 3) * rho ** 2 - ra ** 2) * gb2
+                             + (sp.Rational(2, 3) * rho ** 2 - rb ** 2) * ga2))
+    e = sp.Float("0.08", 30) * slater + sp.Float("0.72", 30) * b88 + sp.Float("0.19", 30) * vwn + sp.Float("0.81", 30) * lyp
+    return rho, sigma, e, sp.diff(e, rho), sp.diff(e, sigma)
+
+
+@pytest.mark.parametrize("vwn5", [False, True])
+def test_b3lyp_energy_and_derivatives_vs_sympy(vwn5):
+    import sympy as sp
+    rho, sigma, e, dr, ds = _sympy_b3lyp(vwn5)
+    fe = sp.lambdify((rho, sigma), e, "mpmath")
+    fr = sp.lambdify((rho, sigma), dr, "mpmath")
+    fs = sp.lambdify((rho, sigma), ds, "mpmath")
+    mp.mp.dps = 30
+    pts = [(1e-8, 1e-14), (1e-4, 1e-7), (0.01, 1e-4), (0.1, 0.05), (0.5, 0.3), (2.0, 5.0), (30.0, 100.0), (300.0, 1e4), (0.2, 0.0)]
+    r = np.array([p[0] for p in pts])
+    s = np.array([p[1] for p in pts])
+    eo, vro, vso = O.functional(2 if vwn5 else 1, r, s)
+    for k, (rv, sv) in enumerate(pts):
+        E = float(fe(mp.mpf(rv), mp.mpf(sv)))
+        R = float(fr(mp.mpf(rv), mp.mpf(sv)))
+        assert abs(eo[k] - E) <= 1e-12 * abs(E), (rv, sv, eo[k], E)
+        assert abs(vro[k] - R) <= 1e-11 * abs(R), (rv, sv, vro[k], R)
+        if sv > 0:
+            Sd = float(fs(mp.mpf(rv), mp.mpf(sv)))
+            assert abs(vso[k] - Sd) <= 1e-10 * abs(Sd) + 1e-14, (rv, sv, vso[k], Sd)
+
+
+def test_density_cutoff():
+    e, vr, vs = O.functional(1, np.array([1e-13, 0.0]), np.array([1e-20, 0.0]))
+    assert (e == 0).all() and (vr == 0).all() and (vs == 0).all()
+
+
+def test_vxc_is_derivative_of_exc():
+    Z, x = molgen.water(2)
+    m = O.Mol(Z, x)
+    g = m.grid(20, 8, 16)
+    N = m.nbf
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((N, N)) * 0.05
+    P = np.diag([2.0, 1.8, 1.2, 1.2, 1.2, 0.6, 0.6]) + A + A.T
+    e0, V = m.xc(1, g, P)
+    h = 1e-5
+    for (i, j) in [(0, 0), (2, 2), (1, 0), (5, 6), (4, 2), (6, 3)]:
+        D = np.zeros((N, N))
+        D[i, j] = D[j, i] = 1.0
+        ep, _ = m.xc(1, g, P + h * D)
+        em, _ = m.xc(1, g, P - h * D)
+        fd = (ep - em) / (2 * h)
+        an = V[i, j] * (1 if i == j else 2)
+        assert abs(fd - an) < 1e-7 * max(1, abs(an)), (i, j, fd, an)
+
+
+# --------------------------------------------------------------------------
+# SCF
+# --------------------------------------------------------------------------
+def test_h2_textbook_values():
+    gd = _gold("h2_sto3g_hf.json")
+    R = gd["R_bohr"] * BOHR
+    m = O.Mol([1, 1], [[0, 0, 0], [0, 0, R]])
+    S, T, V = m.int1e()
+    eri = m.eri()
+    tol = gd["tolerance"]
+    H = T + V
+    assert abs(S[0, 1] - gd["S12"]) < tol and abs(T[0, 0] - gd["T11"]) < tol and abs(T[0, 1] - gd["T12"]) < tol
+    assert abs(H[0, 0] - gd["H11"]) < tol and abs(H[0, 1] - gd["H12"]) < tol
+    assert abs(m.eri_one(0, 0, 0, 0) - gd["eri_1111"]) < tol
+    assert abs(m.eri_one(0, 0, 1, 1) - gd["eri_1122"]) < tol
+    assert abs(m.eri_one(1, 0, 0, 0) - gd["eri_2111"]) < tol
+    assert abs(m.eri_one(1, 0, 1, 0) - gd["eri_2121"]) < tol
+    r = m.scf(xc=O.XC_HF)
+    assert r["status"] == O.ST_CONVERGED
+    assert abs(r["eps"][0] - gd["eps1"]) < tol and abs(r["eps"][1] - gd["eps2"]) < tol
+    assert abs(r["E"] - gd["E_total"]) < tol
+    assert abs(r["E"] - m.enuc() - gd["E_elec"]) < tol
+    assert eri.size == 6
+
+
+def test_water_hf_published_value():
+    gd = _gold("h2o_sto3g_hf.json")
+    m = O.Mol(gd["Z"], np.array(gd["xyz_bohr"]) * BOHR)
+    assert abs(m.enuc() - gd["E_nuc"]) < 1e-9
+    r = m.scf(xc=O.XC_HF, e_tol=1e-11, comm_tol=1e-9)
+    assert r["status"] == O.ST_CONVERGED
+    assert abs(r["E"] - gd["E_total"]) < gd["tolerance_E"]
+    assert np.abs(r["eps"] - np.array(gd["eps"])).max() < gd["tolerance_eps"]
+
+
+def test_eigh_vs_numpy():
+    rng = np.random.default_rng(7)
+    for n in (1, 2, 7, 30):
+        A = rng.standard_normal((n, n))
+        A = A + A.T
+        w, V = O.eigh(A)
+        assert np.allclose(w, np.linalg.eigvalsh(A), atol=1e-12)
+        assert np.allclose(V @ np.diag(w) @ V.T, A, atol=1e-12)
+        assert np.allclose(V.T @ V, np.eye(n), atol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def water_b3lyp():
+    Z, x = molgen.water(0)
+    m = O.Mol(Z, x)
+    return Z, x, m, m.scf(xc=O.XC_B3LYP)
+
+
+def test_scf_density_invariants(water_b3lyp):
+    Z, x, m, r = water_b3lyp
+    S, T, V = m.int1e()
+    P = r["P"]
+    assert r["status"] == O.ST_CONVERGED
+    assert abs(np.trace(P @ S) - 10) < 1e-10          # tr(PS) = N_e
+    assert np.abs(P @ S @ P - 2 * P).max() < 1e-6       # idempotency PSP = 2P
+    assert np.allclose(P, P.T, atol=1e-14)
+    assert r["gap"] > 0 and r["homo"] < 0
+
+
+def test_integrated_density_is_electron_count(water_b3lyp):
+    Z, x, m, r = water_b3lyp
+    g = m.grid()
+    phi = m.ao(g[:, :3])[:, 0, :]
+    rho = np.einsum("gm,mn,gn->g", phi, r["P"], phi)
+    assert abs((g[:, 3] * rho).sum() - 10) < 1e-4
+
+
+def test_hf_energy_rotation_invariant():
+    Z, x = molgen.water(4)
+    th = 0.7
+    Rz = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    e1 = O.Mol(Z, x).scf(xc=O.XC_HF, e_tol=1e-12, comm_tol=1e-9)["E"]
+    e2 = O.Mol(Z, x @ Rz.T).scf(xc=O.XC_HF, e_tol=1e-12, comm_tol=1e-9)["E"]
+    assert abs(e1 - e2) < 1e-10
+
+
+def test_rejects_invalid_input():
+    with pytest.raises(ValueError):
+        O.Mol([1], np.zeros((1, 3)))                      # odd electron count
+    with pytest.raises(ValueError):
+        O.Mol([2, 2], np.array([[0, 0, 0], [1, 0, 0.]]))  # unsupported element
+    with pytest.raises(ValueError):
+        O.Mol([1, 1], np.array([[0, 0, 0], [0, 0, 0.01]]))  # coincident atoms
+    with pytest.raises(ValueError):
+        O.Mol([1, 1], np.array([[0, 0, 0], [0, 0, float("nan")]]))
