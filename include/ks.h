@@ -1,0 +1,181 @@
+/*
+ * ks.h -- C ABI of libks.so: restricted Kohn-Sham (B3LYP / STO-3G) Fock builds
+ * and SCF solves for batches of molecules on one MI355X (gfx950).
+ *
+ * The method is the one of arxiv 2311.01135, section 3.1 ("DFT Primer"): the
+ * inputs are atomic positions and atomic numbers; iteration 0 precomputes
+ * V, T, S and the two-electron integrals I and initialises C; each iteration
+ * forms rho = C D C^T (D = 2 on the N_e/2 lowest orbitals), V_XC(rho),
+ * J_kl = sum_ij I_ijkl rho_ij and K_il = -1/2 sum_jk I_ijkl rho_jk, and
+ * solves [V + T + J + K + V_XC] C = S C eps; the HL gap is read from eps.
+ * Section 3.2 fixes B3LYP, float32 as the working precision, the 8-fold ERI
+ * symmetry and the J/K digestion of the packed integrals; section 5
+ * ("Recomputation", "Multiple IPUs") the integral-direct and split variants.
+ *
+ * Conventions (all entry points):
+ *   - Every function returns ks_status (0 = KS_OK, < 0 = error) and never
+ *     throws across the ABI; ks_last_error() returns a thread-local message
+ *     for the last failing call on this thread.
+ *   - Positions are in Angstrom and converted once with 0.52917721092 A/bohr;
+ *     energies are in Hartree.
+ *   - AO order is atom-major; per H atom 1s; per C/N/O/F atom 1s, 2s, 2px,
+ *     2py, 2pz.  Contracted functions are normalised (S_mm = 1).
+ *   - Per-molecule N x N matrices passed as device pointers are concatenated
+ *     row-major blocks in molecule order: molecule m starts at element
+ *     sum_{m' < m} nbf(m')^2.  ks_batch_sizes() gives nbf(m).
+ *   - Device pointers are borrowed, FP64, and used in stream order on the
+ *     stream given to ks_batch_create (NULL = the null stream).  Host output
+ *     buffers are caller-allocated.  The library owns all other device
+ *     memory, which ks_batch_destroy releases.
+ *   - One handle is used by one host thread at a time.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KS_OK = 0,
+    KS_EINVAL = -1,         /* bad argument or molecule (see ks_last_error) */
+    KS_ENOMEM = -2,         /* device allocation or HBM budget */
+    KS_EDEVICE = -3,        /* HIP runtime error */
+    KS_ENOCONV = -4,        /* reserved */
+    KS_EUNSUPPORTED = -5,   /* option or size outside what is built */
+    KS_ESTATE = -6          /* call out of order (e.g. jk_build before eri_build) */
+} ks_status;
+
+typedef enum {
+    KS_XC_HF = 0,           /* Hartree-Fock: no XC, full exchange */
+    KS_XC_B3LYP = 1,        /* 0.08 Slater + 0.72 B88 + 0.19 VWN(RPA) + 0.81 LYP + 0.20 HF */
+    KS_XC_B3LYP5 = 2        /* the same with VWN5 */
+} ks_xc;
+
+typedef enum {
+    KS_FP64 = 0,            /* every step in FP64 */
+    KS_MIXED = 1            /* ERIs, J/K and XC in FP32 with FP32 accumulation;
+                               Loewdin, eigensolve, DIIS, Fock assembly and the
+                               energy sum in FP64 */
+} ks_precision;
+
+/* per-molecule status (ks_get_result) */
+#define KS_MOL_ACTIVE 0
+#define KS_MOL_CONVERGED 1
+#define KS_MOL_MAXITER 2
+#define KS_MOL_DIVERGED 3
+
+typedef struct {
+    int xc;                 /* ks_xc */
+    int prec;               /* ks_precision */
+    int n_rad, n_theta, n_phi;   /* grid per atom: Treutler radial x Gauss-Legendre(cos theta) x trapezoid(phi) */
+    double e_tol;           /* |E_k - E_{k-1}| threshold (Hartree) */
+    double comm_tol;        /* max |X^T (FPS - SPF) X| threshold */
+    int max_iter;
+    int diis_space;         /* <= 8 */
+    int jk_chunks;          /* work groups per molecule for J/K (0 = automatic) */
+    int xc_chunks;          /* work groups per molecule for XC (0 = automatic) */
+} ks_options;
+
+/* Fills *o with the defaults: B3LYP, FP64, 50 x 12 x 24 grid, e_tol 1e-9,
+ * comm_tol 1e-7, max_iter 100, diis_space 8, automatic chunking. */
+void ks_default_options(ks_options* o);
+
+typedef struct ks_batch ks_batch;
+
+/* Creates a batch of n_mol molecules (paper section 3.1: positions and atomic
+ * numbers in).  n_atoms[n_mol]; Z and xyz_angstrom are concatenated over the
+ * molecules (3 coordinates per atom); charge[n_mol] or NULL for neutral.
+ * stream is a hipStream_t or NULL.  Host prep runs here and the basis,
+ * pair tables and grid nodes are uploaded; no integrals are computed yet.
+ * Errors: KS_EINVAL for an odd electron count, an element outside
+ * {H, C, N, O, F}, non-finite coordinates or atoms closer than 0.1 bohr;
+ * KS_EUNSUPPORTED for a molecule with more than 82 basis functions in
+ * KS_FP64 (96 in KS_MIXED): the J/K digest keeps 3 N^2 values in 160 KB LDS;
+ * KS_ENOMEM / KS_EDEVICE for allocation or runtime failures.  On error *out
+ * is NULL and nothing is leaked. */
+ks_status ks_batch_create(const ks_options* opt, int n_mol, const int* n_atoms, const int* Z,
+                          const double* xyz_angstrom, const int* charge, void* stream,
+                          ks_batch** out);
+
+/* Sizes of molecule mol: basis functions, occupied orbitals, packed unique
+ * ERIs nbf2*(nbf2+1)/2 with nbf2 = nbf*(nbf+1)/2, and grid points.  Any
+ * output pointer may be NULL. */
+ks_status ks_batch_sizes(const ks_batch* b, int mol, int* nbf, int* nocc, long* n_eri, long* n_grid);
+
+/* Number of unique contracted shell quartets of the whole batch (2s and 2p
+ * counted as separate shells), i.e. the ERI work items of eri_build. */
+ks_status ks_batch_quartets(const ks_batch* b, long* n_quartets, long* n_primitive_quartets);
+
+/* One-electron integrals S, T, V (paper section 3.1, iteration 0), Loewdin
+ * X = S^-1/2, the grid with Becke weights and the core-Hamiltonian guess.
+ * Called by scf_solve/scf_step when needed; explicit calls are for parity
+ * tests.  KS_EINVAL if a molecule's overlap has an eigenvalue below 1e-8. */
+ks_status ks_setup(ks_batch* b);
+
+/* Electron-repulsion integrals over the unique shell quartets (8-fold
+ * symmetry, paper section 3.2 "Libcint"), resident on the device in FP64
+ * (KS_FP64) or FP32 (KS_MIXED). */
+ks_status eri_build(ks_batch* b);
+
+/* J and K of every molecule for the densities P_dev (paper section 3.1:
+ * J_kl = sum_ij I_ijkl P_ij, and K_il = sum_jk I_ijkl P_jk, i.e. the
+ * paper's K without its -1/2).  P_dev, J_dev, K_dev: device FP64 blocks as
+ * in the conventions.  KS_ESTATE before eri_build. */
+ks_status jk_build(ks_batch* b, const void* P_dev, void* J_dev, void* K_dev);
+
+/* V_XC and E_XC for the densities P_dev on the Becke grid (B3LYP; zero for
+ * KS_XC_HF).  Vxc_dev: device FP64 blocks; Exc_host[n_mol] host doubles. */
+ks_status xc_build(ks_batch* b, const void* P_dev, void* Vxc_dev, double* Exc_host);
+
+/* Fock matrices F = H + J - (a0/2) K + V_XC for P_dev (or the resident
+ * density when P_dev is NULL) and the energy terms, host E_terms[n_mol*6] =
+ * {tr PH, 1/2 tr PJ, -a0/4 tr PK, E_xc, E_nn, E_total}.  F_dev may be NULL. */
+ks_status fock_build(ks_batch* b, const void* P_dev, void* F_dev, double* E_terms);
+
+/* One SCF iteration for every active molecule (Fock build, DIIS, eigen-
+ * solve, new density, convergence test).  *n_active = molecules still
+ * iterating afterwards. */
+ks_status scf_step(ks_batch* b, int* n_active);
+
+/* Iterates until every molecule has converged or reached max_iter.  A
+ * molecule that does not converge gets status KS_MOL_MAXITER; the call
+ * still returns KS_OK. */
+ks_status scf_solve(ks_batch* b);
+
+/* Results of molecule mol (host buffers; eps[nbf] and P[nbf*nbf] may be
+ * NULL).  gap = eps_LUMO - eps_HOMO (> 0); eps are the eigenvalues of the
+ * last un-extrapolated Fock matrix and P the density that produced it. */
+ks_status ks_get_result(const ks_batch* b, int mol, double* E, double* eps, double* P, double* homo,
+                        double* lumo, double* gap, int* status, int* n_iter);
+
+/* Packed unique ERIs of molecule mol in FP64 (out[n_eri]), index
+ * ij(ij+1)/2 + kl with ij = i(i+1)/2 + j, i >= j, k >= l, ij >= kl. */
+ks_status ks_get_eri(const ks_batch* b, int mol, double* out);
+
+/* Copies a resident N x N matrix of molecule mol to the host:
+ * which = 0 S, 1 T, 2 V(nuclear), 3 X = S^-1/2, 4 F, 5 P, 6 J, 7 K, 8 V_xc. */
+ks_status ks_get_matrix(const ks_batch* b, int mol, int which, double* out);
+
+/* Grid points (x, y, z, w) in bohr of molecule mol: out[n_grid*4]. */
+ks_status ks_get_grid(const ks_batch* b, int mol, double* out);
+
+/* Average device time in milliseconds of the last launch of each kernel
+ * family, measured with HIP events on the batch stream when timing is on
+ * (ks_set_timing).  names/values arrays of length cap; returns count. */
+int ks_kernel_times(const ks_batch* b, const char** names, double* ms, int cap);
+void ks_set_timing(ks_batch* b, int on);
+
+/* Releases the batch and all of its device memory.  NULL-safe. */
+void ks_batch_destroy(ks_batch* b);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* ks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KS_H */

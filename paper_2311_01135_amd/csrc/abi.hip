@@ -1,0 +1,757 @@
+// C ABI of libks.so: host preparation of a batch (basis, shell pairs, quartet
+// classes, grid nodes, work items), device memory layout, and the SCF driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "kernels.h"
+
+namespace ks {
+
+// ---------------------------------------------------------------------------
+// errors and timing
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+KTimer::KTimer(ks_batch* b_, const char* n) : b(b_), name(n)
+{
+    if (b->timing) {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, b->stream);
+    }
+}
+
+KTimer::~KTimer()
+{
+    if (!b->timing) return;
+    (void)hipEventRecord(e1, b->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (size_t i = 0; i < b->tnames.size(); i++)
+        if (b->tnames[i] == name) {
+            b->tms[2 * i] += ms;
+            b->tms[2 * i + 1] += 1.0;
+            return;
+        }
+    b->tnames.push_back(name);
+    b->tms.push_back(ms);
+    b->tms.push_back(1.0);
+}
+
+// ---------------------------------------------------------------------------
+// STO-3G (Hehre, Stewart, Pople 1969): universal zeta = 1 Gaussian expansions,
+// scaled per element and shell by zeta^2.
+// ---------------------------------------------------------------------------
+struct Sto3g {
+    double a1s[3] = {2.227660584, 0.4057711562, 0.1098175104};
+    double d1s[3] = {0.1543289673, 0.5353281423, 0.4446345422};
+    double a2sp[3] = {0.9942027, 0.2310313, 0.0751386};
+    double d2s[3] = {-0.09996723, 0.39951283, 0.70011547};
+    double d2p[3] = {0.15591627, 0.60768372, 0.39195739};
+};
+
+static bool element_zetas(int Z, double& z1s, double& z2sp)
+{
+    switch (Z) {
+    case 1: z1s = 1.24; z2sp = 0.0; return true;
+    case 6: z1s = 5.67; z2sp = 1.72; return true;
+    case 7: z1s = 6.67; z2sp = 1.95; return true;
+    case 8: z1s = 7.66; z2sp = 2.25; return true;
+    case 9: z1s = 8.65; z2sp = 2.55; return true;
+    default: return false;
+    }
+}
+
+// contraction coefficients x primitive norms, renormalised so <phi|phi> = 1
+static void make_shell(Shell& s, int L, const double* a0, double zeta, const double* d)
+{
+    s.L = L;
+    for (int k = 0; k < 3; k++) {
+        s.a[k] = a0[k] * zeta * zeta;
+        const double n = std::pow(2.0 * s.a[k] / kPi, 0.75) * (L ? 2.0 * std::sqrt(s.a[k]) : 1.0);
+        s.c[k] = d[k] * n;
+    }
+    double norm = 0.0;
+    for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++) {
+            const double p = s.a[k] + s.a[l];
+            norm += s.c[k] * s.c[l] * std::pow(kPi / p, 1.5) * (L ? 0.5 / p : 1.0);
+        }
+    for (int k = 0; k < 3; k++) s.c[k] /= std::sqrt(norm);
+}
+
+// Treutler-Ahlrichs M4 (xi = 1, alpha = 0.6) on Chebyshev nodes of the 2nd kind:
+// r = (1/ln2)(1+x)^0.6 ln(2/(1-x)), w = pi/(n+1) sin(theta_i) dr/dx r^2.
+static void radial_rule(int n, std::vector<double>& out)
+{
+    out.assign(2 * n, 0.0);
+    const double al = 0.6, il2 = 1.0 / std::log(2.0);
+    for (int i = 1; i <= n; i++) {
+        const double th = i * kPi / (n + 1), x = std::cos(th);
+        const double lg = std::log(2.0 / (1.0 - x));
+        const double r = il2 * std::pow(1.0 + x, al) * lg;
+        const double drdx = il2 * (al * std::pow(1.0 + x, al - 1.0) * lg + std::pow(1.0 + x, al) / (1.0 - x));
+        out[i - 1] = r;
+        out[n + i - 1] = kPi / (n + 1) * std::sin(th) * drdx * r * r;
+    }
+}
+
+// Gauss-Legendre nodes in cos(theta) by Newton's method on the three-term
+// recurrence; weights 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss_legendre(int n, std::vector<double>& out)
+{
+    out.assign(2 * n, 0.0);
+    for (int i = 0; i < n; i++) {
+        long double x = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0L;
+        for (int it = 0; it < 200; it++) {
+            long double p0 = 1.0L, p1 = x;
+            for (int k = 2; k <= n; k++) {
+                const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p0 = 1.0L; p1 = x; }
+            dp = n * (x * p1 - p0) / (x * x - 1.0L);
+            const long double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs((double)dx) < 1e-19) break;
+        }
+        {
+            long double p0 = 1.0L, p1 = x;
+            for (int k = 2; k <= n; k++) {
+                const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p0 = 1.0L; p1 = x; }
+            dp = n * (x * p1 - p0) / (x * x - 1.0L);
+        }
+        out[i] = (double)x;
+        out[n + i] = (double)(2.0L / ((1.0L - x * x) * dp * dp));
+    }
+}
+
+}  // namespace ks
+
+using namespace ks;
+
+// ---------------------------------------------------------------------------
+// allocation helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+static ks_status dev_alloc(ks_batch* b, T** p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess) {
+        set_error("hipMalloc(%zu bytes) failed: %s", n * sizeof(T), hipGetErrorString(e));
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? KS_ENOMEM : KS_EDEVICE;
+    }
+    b->allocs.push_back(q);
+    *p = (T*)q;
+    return KS_OK;
+}
+
+template <typename T>
+static ks_status upload(ks_batch* b, T** p, const std::vector<T>& v)
+{
+    ks_status st = dev_alloc(b, p, v.size());
+    if (st) return st;
+    if (!v.empty()) KS_HIP(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, b->stream));
+    return KS_OK;
+}
+
+static void free_batch(ks_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    else (void)hipDeviceSynchronize();
+    for (void* p : b->allocs) (void)hipFree(p);
+    if (b->h_nactive) (void)hipHostFree(b->h_nactive);
+    delete b;
+}
+
+extern "C" {
+
+void ks_default_options(ks_options* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->xc = KS_XC_B3LYP;
+    o->prec = KS_FP64;
+    o->n_rad = 50;
+    o->n_theta = 12;
+    o->n_phi = 24;
+    o->e_tol = 1e-9;
+    o->comm_tol = 1e-7;
+    o->max_iter = 100;
+    o->diis_space = 8;
+    o->jk_chunks = 0;
+    o->xc_chunks = 0;
+}
+
+const char* ks_last_error(void) { return g_err; }
+
+static ks_status create_impl(const ks_options* opt, int n_mol, const int* n_atoms, const int* Z, const double* xyz,
+                             const int* charge, void* stream, ks_batch* b);
+
+ks_status ks_batch_create(const ks_options* opt, int n_mol, const int* n_atoms, const int* Z,
+                          const double* xyz_angstrom, const int* charge, void* stream, ks_batch** out)
+{
+    g_err[0] = 0;
+    if (!out) {
+        set_error("out is NULL");
+        return KS_EINVAL;
+    }
+    *out = nullptr;
+    ks_batch* b = new (std::nothrow) ks_batch();
+    if (!b) {
+        set_error("host allocation failed");
+        return KS_ENOMEM;
+    }
+    ks_status st = create_impl(opt, n_mol, n_atoms, Z, xyz_angstrom, charge, stream, b);
+    if (st != KS_OK) {
+        free_batch(b);
+        return st;
+    }
+    *out = b;
+    return KS_OK;
+}
+
+void ks_batch_destroy(ks_batch* b) { free_batch(b); }
+
+}  // extern "C"
+
+static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_atoms, const int* Zin, const double* xyz,
+                             const int* charge, void* stream, ks_batch* b)
+{
+    ks_options opt;
+    ks_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (n_mol <= 0 || !n_atoms || !Zin || !xyz) {
+        set_error("n_mol must be > 0 and n_atoms, Z, xyz non-NULL");
+        return KS_EINVAL;
+    }
+    if (opt.xc < KS_XC_HF || opt.xc > KS_XC_B3LYP5 || (opt.prec != KS_FP64 && opt.prec != KS_MIXED)) {
+        set_error("unknown xc or precision option");
+        return KS_EINVAL;
+    }
+    if (opt.n_rad < 1 || opt.n_theta < 1 || opt.n_phi < 1 || opt.max_iter < 1 || opt.diis_space < 1 ||
+        opt.diis_space > kMaxDiis || !(opt.e_tol > 0) || !(opt.comm_tol > 0)) {
+        set_error("grid sizes, max_iter >= 1, 1 <= diis_space <= %d and positive tolerances required", kMaxDiis);
+        return KS_EINVAL;
+    }
+    b->opt = opt;
+    b->stream = (hipStream_t)stream;
+    b->n_mol = n_mol;
+    b->a0 = opt.xc == KS_XC_HF ? 1.0 : 0.20;
+    const int maxn = opt.prec == KS_MIXED ? kMaxNbf : 82;
+    Sto3g sto;
+
+    long atom0 = 0, mat0 = 0, grid0 = 0, ao0 = 0;
+    long qoff[kNClass] = {0, 0, 0, 0, 0, 0};
+    std::vector<Pair> pairs[3];
+    std::vector<int2> aoinfo;
+    std::vector<long> qprefix[kNClass];
+    for (int c = 0; c < kNClass; c++) qprefix[c].push_back(0);
+    const long per_atom = (long)opt.n_rad * opt.n_theta * opt.n_phi;
+    b->mol.resize(n_mol);
+    for (int m = 0; m < n_mol; m++) {
+        MolDesc& md = b->mol[m];
+        std::memset(&md, 0, sizeof(md));
+        const int na = n_atoms[m];
+        if (na <= 0) {
+            set_error("molecule %d: n_atoms must be > 0", m);
+            return KS_EINVAL;
+        }
+        int ne = -(charge ? charge[m] : 0), nbf = 0;
+        md.natom = na;
+        md.atom0 = (int)atom0;
+        md.shell0 = (int)b->shells.size();
+        for (int a = 0; a < na; a++) {
+            const int z = Zin[atom0 + a];
+            double z1, z2;
+            if (!element_zetas(z, z1, z2)) {
+                set_error("molecule %d atom %d: element Z=%d is not in {H, C, N, O, F}", m, a, z);
+                return KS_EINVAL;
+            }
+            double p[3];
+            for (int k = 0; k < 3; k++) {
+                const double v = xyz[3 * (atom0 + a) + k];
+                if (!std::isfinite(v)) {
+                    set_error("molecule %d atom %d: non-finite coordinate", m, a);
+                    return KS_EINVAL;
+                }
+                p[k] = v / kBohrAng;
+            }
+            for (int c = 0; c < a; c++) {
+                const double* q = &b->R[3 * (atom0 + c)];
+                const double d = std::sqrt((p[0] - q[0]) * (p[0] - q[0]) + (p[1] - q[1]) * (p[1] - q[1]) + (p[2] - q[2]) * (p[2] - q[2]));
+                if (d < 0.1) {
+                    set_error("molecule %d: atoms %d and %d closer than 0.1 bohr", m, c, a);
+                    return KS_EINVAL;
+                }
+            }
+            b->Z.push_back(z);
+            for (int k = 0; k < 3; k++) b->R.push_back(p[k]);
+            ne += z;
+            Shell s{};
+            for (int k = 0; k < 3; k++) s.A[k] = p[k];
+            s.atom = a;
+            make_shell(s, 0, sto.a1s, z1, sto.d1s);
+            s.ao = nbf;
+            b->shells.push_back(s);
+            nbf += 1;
+            if (z > 1) {
+                make_shell(s, 0, sto.a2sp, z2, sto.d2s);
+                s.ao = nbf;
+                b->shells.push_back(s);
+                nbf += 1;
+                make_shell(s, 1, sto.a2sp, z2, sto.d2p);
+                s.ao = nbf;
+                b->shells.push_back(s);
+                nbf += 3;
+            }
+        }
+        if (ne <= 0 || (ne & 1)) {
+            set_error("molecule %d: %d electrons; the restricted method needs a positive even count", m, ne);
+            return KS_EINVAL;
+        }
+        if (nbf > maxn) {
+            set_error("molecule %d: %d basis functions exceeds the %d supported in this precision", m, nbf, maxn);
+            return KS_EUNSUPPORTED;
+        }
+        md.nbf = nbf;
+        md.nocc = ne / 2;
+        if (md.nocc > nbf) {
+            set_error("molecule %d: more occupied orbitals than basis functions", m);
+            return KS_EINVAL;
+        }
+        md.nshell = (int)b->shells.size() - md.shell0;
+        md.np = (nbf + 15) / 16 * 16;
+        md.ao0 = (int)ao0;
+        md.mat0 = mat0;
+        md.grid0 = grid0;
+        md.ngrid = (long)na * per_atom;
+        double enuc = 0.0;
+        for (int a = 0; a < na; a++)
+            for (int c = 0; c < a; c++) {
+                const double* p = &b->R[3 * (atom0 + a)];
+                const double* q = &b->R[3 * (atom0 + c)];
+                enuc += Zin[atom0 + a] * Zin[atom0 + c] /
+                        std::sqrt((p[0] - q[0]) * (p[0] - q[0]) + (p[1] - q[1]) * (p[1] - q[1]) + (p[2] - q[2]) * (p[2] - q[2]));
+            }
+        md.enuc = enuc;
+        // AO table
+        for (int s = md.shell0; s < md.shell0 + md.nshell; s++)
+            for (int c = 0; c < (b->shells[s].L ? 3 : 1); c++) aoinfo.push_back(make_int2(s, c));
+        // shell pairs by class (the p shell first in ps pairs)
+        for (int c = 0; c < 3; c++) md.pair0[c] = (int)pairs[c].size();
+        for (int sa = md.shell0; sa < md.shell0 + md.nshell; sa++)
+            for (int sb = md.shell0; sb <= sa; sb++) {
+                const int la = b->shells[sa].L, lb = b->shells[sb].L;
+                if (la + lb == 1) pairs[1].push_back(la ? Pair{sa, sb} : Pair{sb, sa});
+                else pairs[la + lb].push_back(Pair{sa, sb});
+            }
+        for (int c = 0; c < 3; c++) md.npair[c] = (int)pairs[c].size() - md.pair0[c];
+        for (int c = 0; c < kNClass; c++) {
+            const long nb = md.npair[class_bra(c)], nk = md.npair[class_ket(c)];
+            md.nq[c] = class_tri(c) ? nb * (nb + 1) / 2 : nb * nk;
+            md.q0[c] = qoff[c];
+            qoff[c] += md.nq[c];
+            qprefix[c].push_back(qoff[c]);
+            b->nprimq += md.nq[c] * kNPrimPair * kNPrimPair;
+        }
+        atom0 += na;
+        mat0 += (long)nbf * nbf;
+        grid0 += md.ngrid;
+        ao0 += nbf;
+        b->max_np = std::max(b->max_np, md.np);
+    }
+    b->nmat = mat0;
+    b->ngrid = grid0;
+    for (int c = 0; c < 3; c++) b->npairs[c] = (long)pairs[c].size();
+    for (int c = 0; c < kNClass; c++) b->nq[c] = qoff[c];
+
+    // work items
+    const int jk_chunks = opt.jk_chunks > 0 ? opt.jk_chunks : std::max(1, std::min(64, (512 + n_mol - 1) / n_mol));
+    for (int m = 0; m < n_mol; m++)
+        for (int c = 0; c < jk_chunks; c++) b->jk_items.push_back(JkItem{m, c, jk_chunks, 0});
+    const int bp = opt.prec == KS_MIXED ? 64 : 32;
+    std::vector<int> xc_first;
+    for (int m = 0; m < n_mol; m++) {
+        xc_first.push_back((int)b->xc_items.size());
+        const MolDesc& md = b->mol[m];
+        long nch = opt.xc_chunks > 0 ? opt.xc_chunks : std::max(1, (2048 + n_mol - 1) / n_mol);
+        nch = std::max(1L, std::min(nch, md.ngrid / (4L * bp)));
+        for (long c = 0; c < nch; c++) {
+            XcItem it{};
+            it.mol = m;
+            it.g0 = md.ngrid * c / nch;
+            it.g1 = md.ngrid * (c + 1) / nch;
+            b->xc_items.push_back(it);
+        }
+    }
+    xc_first.push_back((int)b->xc_items.size());
+
+    // device memory
+    ks_status st;
+    std::vector<double> tab, rad, ang, Zc(b->Z.begin(), b->Z.end());
+    build_boys_table(tab);
+    std::vector<float> tabf(tab.begin(), tab.end());
+    radial_rule(opt.n_rad, rad);
+    gauss_legendre(opt.n_theta, ang);
+    std::vector<long> ptoff;
+    long pt = 0;
+    for (auto& md : b->mol) {
+        ptoff.push_back(pt);
+        pt += (long)md.np * md.np;
+    }
+    b->npt_total = pt;
+    if ((st = upload(b, &b->d_mol, b->mol))) return st;
+    if ((st = upload(b, &b->d_shells, b->shells))) return st;
+    if ((st = upload(b, &b->d_aoinfo, aoinfo))) return st;
+    if ((st = upload(b, &b->d_R, b->R))) return st;
+    if ((st = upload(b, &b->d_Zc, Zc))) return st;
+    if ((st = upload(b, &b->d_boys, tab))) return st;
+    if ((st = upload(b, &b->d_boys_f, tabf))) return st;
+    if ((st = upload(b, &b->d_radial, rad))) return st;
+    if ((st = upload(b, &b->d_ang, ang))) return st;
+    if ((st = upload(b, &b->d_ptoff, ptoff))) return st;
+    if ((st = upload(b, &b->d_jk_items, b->jk_items))) return st;
+    if ((st = upload(b, &b->d_xc_items, b->xc_items))) return st;
+    if ((st = upload(b, &b->d_xc_first, xc_first))) return st;
+    for (int c = 0; c < 3; c++) {
+        if ((st = upload(b, &b->d_pairs[c], pairs[c]))) return st;
+        if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair))) return st;
+    }
+    for (int c = 0; c < kNClass; c++)
+        if ((st = upload(b, &b->d_qoff[c], qprefix[c]))) return st;
+    std::vector<MolState> s0(n_mol);
+    std::memset(s0.data(), 0, sizeof(MolState) * n_mol);
+    if ((st = upload(b, &b->d_state, s0))) return st;
+    double** mats[] = {&b->d_S, &b->d_T, &b->d_V, &b->d_H, &b->d_X, &b->d_F, &b->d_P,
+                       &b->d_J, &b->d_K, &b->d_Vxc, &b->d_Fp, &b->d_C};
+    for (double** p : mats)
+        if ((st = dev_alloc(b, p, (size_t)b->nmat))) return st;
+    if ((st = dev_alloc(b, &b->d_eps, (size_t)ao0))) return st;
+    if ((st = dev_alloc(b, &b->d_work, 3 * (size_t)b->nmat))) return st;
+    if ((st = dev_alloc(b, &b->d_Fh, (size_t)opt.diis_space * b->nmat))) return st;
+    if ((st = dev_alloc(b, &b->d_Eh, (size_t)opt.diis_space * b->nmat))) return st;
+    const size_t es = opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
+    const size_t np2 = (size_t)b->max_np * b->max_np;
+    unsigned char* tmp;
+    if ((st = dev_alloc(b, &tmp, es * (size_t)pt))) return st;
+    b->d_Pt = tmp;
+    if ((st = dev_alloc(b, &tmp, es * 2 * np2 * b->jk_items.size()))) return st;
+    b->d_jk_part = tmp;
+    if ((st = dev_alloc(b, &tmp, es * np2 * b->xc_items.size()))) return st;
+    b->d_xc_part = tmp;
+    if ((st = dev_alloc(b, &b->d_xc_exc, b->xc_items.size()))) return st;
+    if ((st = dev_alloc(b, &b->d_exc, (size_t)n_mol))) return st;
+    if ((st = dev_alloc(b, &b->d_nactive, 1))) return st;
+    if ((st = dev_alloc(b, &b->d_eterms, 6 * (size_t)n_mol))) return st;
+    KS_HIP(hipHostMalloc((void**)&b->h_nactive, sizeof(int), hipHostMallocDefault));
+    KS_HIP(hipMemsetAsync(b->d_Vxc, 0, sizeof(double) * b->nmat, b->stream));
+    KS_HIP(hipMemsetAsync(b->d_exc, 0, sizeof(double) * n_mol, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    return KS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+#define CHECK_B(b)                             \
+    do {                                       \
+        g_err[0] = 0;                          \
+        if (!(b)) {                            \
+            set_error("batch handle is NULL"); \
+            return KS_EINVAL;                  \
+        }                                      \
+    } while (0)
+
+extern "C" {
+
+ks_status ks_batch_sizes(const ks_batch* b, int mol, int* nbf, int* nocc, long* n_eri, long* n_grid)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol) {
+        set_error("molecule index %d out of range", mol);
+        return KS_EINVAL;
+    }
+    const MolDesc& md = b->mol[mol];
+    const long np = (long)md.nbf * (md.nbf + 1) / 2;
+    if (nbf) *nbf = md.nbf;
+    if (nocc) *nocc = md.nocc;
+    if (n_eri) *n_eri = np * (np + 1) / 2;
+    if (n_grid) *n_grid = md.ngrid;
+    return KS_OK;
+}
+
+ks_status ks_batch_quartets(const ks_batch* b, long* nq, long* nprim)
+{
+    CHECK_B(b);
+    long t = 0;
+    for (int c = 0; c < kNClass; c++) t += b->nq[c];
+    if (nq) *nq = t;
+    if (nprim) *nprim = b->nprimq;
+    return KS_OK;
+}
+
+ks_status ks_setup(ks_batch* b)
+{
+    CHECK_B(b);
+    if (b->setup_done) return KS_OK;
+    ks_status st;
+    if ((st = launch_pairs(b))) return st;
+    if ((st = launch_int1e(b))) return st;
+    if ((st = launch_lowdin(b))) return st;
+    std::vector<MolState> s(b->n_mol);
+    KS_HIP(hipMemcpyAsync(s.data(), b->d_state, sizeof(MolState) * b->n_mol, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    for (int m = 0; m < b->n_mol; m++)
+        if (s[m].status == -1) {
+            set_error("molecule %d: near-singular overlap (smallest eigenvalue < 1e-8)", m);
+            return KS_EINVAL;
+        }
+    if (b->opt.xc != KS_XC_HF) {
+        if ((st = dev_alloc(b, &b->d_grid, 4 * (size_t)b->ngrid))) return st;
+        if ((st = launch_grid(b))) return st;
+    }
+    if ((st = launch_guess(b))) return st;
+    b->setup_done = true;
+    b->guess_done = true;
+    return KS_OK;
+}
+
+ks_status eri_build(ks_batch* b)
+{
+    CHECK_B(b);
+    if (b->eri_done) return KS_OK;
+    ks_status st;
+    if (!b->setup_done && (st = ks_setup(b))) return st;
+    const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
+    for (int c = 0; c < kNClass; c++) {
+        unsigned char* p;
+        if ((st = dev_alloc(b, &p, es * (size_t)b->nq[c] * class_ncomp(c)))) return st;
+        b->d_eri[c] = p;
+    }
+    if ((st = launch_eri(b))) return st;
+    b->eri_done = true;
+    return KS_OK;
+}
+
+ks_status jk_build(ks_batch* b, const void* P, void* J, void* K)
+{
+    CHECK_B(b);
+    if (!P || !J || !K) {
+        set_error("P, J and K must be device pointers");
+        return KS_EINVAL;
+    }
+    if (!b->eri_done) {
+        set_error("jk_build before eri_build");
+        return KS_ESTATE;
+    }
+    ks_status st = launch_jk(b, (const double*)P, (double*)J, (double*)K, false);
+    if (st) return st;
+    KS_HIP(hipStreamSynchronize(b->stream));
+    return KS_OK;
+}
+
+ks_status xc_build(ks_batch* b, const void* P, void* V, double* Exc)
+{
+    CHECK_B(b);
+    if (!P || !V) {
+        set_error("P and Vxc must be device pointers");
+        return KS_EINVAL;
+    }
+    ks_status st;
+    if (!b->setup_done && (st = ks_setup(b))) return st;
+    if (b->opt.xc == KS_XC_HF) {
+        KS_HIP(hipMemsetAsync(V, 0, sizeof(double) * b->nmat, b->stream));
+        KS_HIP(hipStreamSynchronize(b->stream));
+        if (Exc)
+            for (int m = 0; m < b->n_mol; m++) Exc[m] = 0.0;
+        return KS_OK;
+    }
+    if ((st = launch_xc(b, (const double*)P, (double*)V, false))) return st;
+    if (Exc) KS_HIP(hipMemcpyAsync(Exc, b->d_exc, sizeof(double) * b->n_mol, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    return KS_OK;
+}
+
+ks_status fock_build(ks_batch* b, const void* Pin, void* F, double* E_terms)
+{
+    CHECK_B(b);
+    ks_status st;
+    if (!b->eri_done && (st = eri_build(b))) return st;
+    const double* P = Pin ? (const double*)Pin : b->d_P;
+    if ((st = launch_jk(b, P, b->d_J, b->d_K, false))) return st;
+    if (b->opt.xc != KS_XC_HF) {
+        if ((st = launch_xc(b, P, b->d_Vxc, false))) return st;
+    }
+    double* Fo = F ? (double*)F : b->d_work;
+    if ((st = launch_fock(b, P, b->d_J, b->d_K, b->d_Vxc, Fo, false, b->d_eterms))) return st;
+    if (E_terms)
+        KS_HIP(hipMemcpyAsync(E_terms, b->d_eterms, sizeof(double) * 6 * b->n_mol, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    return KS_OK;
+}
+
+ks_status scf_step(ks_batch* b, int* n_active)
+{
+    CHECK_B(b);
+    ks_status st;
+    if (!b->eri_done && (st = eri_build(b))) return st;
+    if ((st = launch_jk(b, b->d_P, b->d_J, b->d_K, true))) return st;
+    if (b->opt.xc != KS_XC_HF && (st = launch_xc(b, b->d_P, b->d_Vxc, true))) return st;
+    if ((st = launch_fock(b, b->d_P, b->d_J, b->d_K, b->d_Vxc, b->d_F, true, nullptr))) return st;
+    if ((st = launch_iteration_tail(b))) return st;
+    if ((st = launch_count_active(b))) return st;
+    KS_HIP(hipMemcpyAsync(b->h_nactive, b->d_nactive, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    b->iter++;
+    if (n_active) *n_active = *b->h_nactive;
+    return KS_OK;
+}
+
+ks_status scf_solve(ks_batch* b)
+{
+    CHECK_B(b);
+    ks_status st;
+    for (int it = 0; it <= b->opt.max_iter + 1; it++) {
+        int na = 0;
+        if ((st = scf_step(b, &na))) return st;
+        if (na == 0) return KS_OK;
+    }
+    set_error("scf_solve: molecules still active after max_iter + 2 steps");
+    return KS_ESTATE;
+}
+
+ks_status ks_get_result(const ks_batch* b, int mol, double* E, double* eps, double* P, double* homo, double* lumo,
+                        double* gap, int* status, int* n_iter)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol) {
+        set_error("molecule index %d out of range", mol);
+        return KS_EINVAL;
+    }
+    const MolDesc& md = b->mol[mol];
+    MolState s;
+    std::vector<double> e(md.nbf);
+    KS_HIP(hipMemcpyAsync(&s, b->d_state + mol, sizeof(MolState), hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipMemcpyAsync(e.data(), b->d_eps + md.ao0, sizeof(double) * md.nbf, hipMemcpyDeviceToHost, b->stream));
+    if (P) KS_HIP(hipMemcpyAsync(P, b->d_P + md.mat0, sizeof(double) * md.nbf * md.nbf, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    if (E) *E = s.E;
+    if (eps) std::memcpy(eps, e.data(), sizeof(double) * md.nbf);
+    const double h = e[md.nocc - 1], l = md.nocc < md.nbf ? e[md.nocc] : NAN;
+    if (homo) *homo = h;
+    if (lumo) *lumo = l;
+    if (gap) *gap = l - h;
+    if (status) *status = s.status;
+    if (n_iter) *n_iter = s.iter;
+    return KS_OK;
+}
+
+ks_status ks_get_eri(const ks_batch* b, int mol, double* out)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol || !out) {
+        set_error("bad molecule index or NULL output");
+        return KS_EINVAL;
+    }
+    if (!b->eri_done) {
+        set_error("ks_get_eri before eri_build");
+        return KS_ESTATE;
+    }
+    long neri;
+    ks_batch_sizes(b, mol, nullptr, nullptr, &neri, nullptr);
+    double* d = nullptr;
+    KS_HIP(hipMalloc(&d, sizeof(double) * neri));
+    ks_status st = launch_eri_unpack(b, mol, d);
+    if (st == KS_OK) {
+        hipError_t e = hipMemcpyAsync(out, d, sizeof(double) * neri, hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) {
+            set_error("ks_get_eri copy failed: %s", hipGetErrorString(e));
+            st = KS_EDEVICE;
+        }
+    }
+    (void)hipFree(d);
+    return st;
+}
+
+ks_status ks_get_matrix(const ks_batch* b, int mol, int which, double* out)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol || !out) {
+        set_error("bad molecule index or NULL output");
+        return KS_EINVAL;
+    }
+    const double* src[] = {b->d_S, b->d_T, b->d_V, b->d_X, b->d_F, b->d_P, b->d_J, b->d_K, b->d_Vxc};
+    if (which < 0 || which > 8) {
+        set_error("matrix selector %d out of range", which);
+        return KS_EINVAL;
+    }
+    const MolDesc& md = b->mol[mol];
+    KS_HIP(hipMemcpyAsync(out, src[which] + md.mat0, sizeof(double) * md.nbf * md.nbf, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    return KS_OK;
+}
+
+ks_status ks_get_grid(const ks_batch* b, int mol, double* out)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol || !out) {
+        set_error("bad molecule index or NULL output");
+        return KS_EINVAL;
+    }
+    if (!b->d_grid) {
+        set_error("no grid (Hartree-Fock batch or ks_setup not called)");
+        return KS_ESTATE;
+    }
+    const MolDesc& md = b->mol[mol];
+    KS_HIP(hipMemcpyAsync(out, b->d_grid + 4 * md.grid0, sizeof(double) * 4 * md.ngrid, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    return KS_OK;
+}
+
+void ks_set_timing(ks_batch* b, int on)
+{
+    if (!b) return;
+    b->timing = on != 0;
+    b->tnames.clear();
+    b->tms.clear();
+}
+
+int ks_kernel_times(const ks_batch* b, const char** names, double* ms, int cap)
+{
+    if (!b) return 0;
+    int n = (int)b->tnames.size();
+    for (int i = 0; i < n && i < cap; i++) {
+        names[i] = b->tnames[i].c_str();
+        ms[i] = b->tms[2 * i] / std::max(1.0, b->tms[2 * i + 1]);
+    }
+    return n;
+}
+
+}  // extern "C"

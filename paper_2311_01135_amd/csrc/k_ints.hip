@@ -1,0 +1,524 @@
+// One- and two-electron integrals over contracted s/p Gaussians by the
+// McMurchie-Davidson scheme (Hermite expansion of Gaussian products and the
+// Hermite Coulomb integrals R_tuv), for gfx950.
+//
+// Paper section 3.2 ("Libcint"): the ERIs are computed once per molecule,
+// each call independent, and stored with their 8-fold symmetry.  Here one
+// lane computes one contracted unique shell quartet; the quartets of a class
+// (ss|ss), (ps|ss), (ps|ps), (pp|ss), (pp|ps), (pp|pp) run in their own
+// fully unrolled kernel so that every lane of a wavefront executes the same
+// instruction stream (the SIMD answer to the paper's MIMD-per-thread port).
+#include <cmath>
+
+#include "kernels.h"
+
+namespace ks {
+
+// ---------------------------------------------------------------------------
+// Boys function
+// ---------------------------------------------------------------------------
+// Table F_m(T_i), T_i = i * DT, from the power series
+// F_m(T) = exp(-T) sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1))   (all terms > 0).
+void build_boys_table(std::vector<double>& tab)
+{
+    tab.assign((size_t)kBoysNT * kBoysM, 0.0);
+    for (int i = 0; i < kBoysNT; i++) {
+        long double T = (long double)i * kBoysDT;
+        for (int m = 0; m < kBoysM; m++) {
+            long double term = 1.0L / (2 * m + 1), sum = term;
+            for (int k = 1; k < 2000; k++) {
+                term *= 2.0L * T / (2 * m + 2 * k + 1);
+                sum += term;
+                if (term < 1e-22L * sum) break;
+            }
+            tab[(size_t)i * kBoysM + m] = (double)(expl(-T) * sum);
+        }
+    }
+}
+
+template <typename R> struct BoysOrder;
+template <> struct BoysOrder<double> { static constexpr int K = 7; };
+template <> struct BoysOrder<float> { static constexpr int K = 4; };
+
+// F_0..F_L at T: Taylor expansion about the nearest table node for the top
+// order (dF_m/dT = -F_{m+1}), downward recursion F_m = (2T F_{m+1} + e^-T)/(2m+1);
+// above the table, F_0 = sqrt(pi/T)/2 and upward recursion.
+template <int L, typename R>
+__device__ __forceinline__ void boys(R T, R (&F)[L + 1], const R* __restrict__ tab)
+{
+    if (T < R(kBoysTMax)) {
+        constexpr int K = BoysOrder<R>::K;
+        int i = (int)(T * R(1.0 / kBoysDT) + R(0.5));
+        R dt = R(i) * R(kBoysDT) - T;
+        const R* row = tab + (size_t)i * kBoysM + L;
+        R s = row[K - 1];
+#pragma unroll
+        for (int k = K - 1; k >= 1; --k) s = row[k - 1] + dt * s * R(1.0 / k);
+        F[L] = s;
+        if (L > 0) {
+            R e = exp(-T);
+#pragma unroll
+            for (int m = L - 1; m >= 0; --m) F[m] = (R(2) * T * F[m + 1] + e) * R(1.0 / (2 * m + 1));
+        }
+    } else {
+        R e = exp(-T), inv = R(1) / T;
+        F[0] = R(0.5) * sqrt(R(kPi) * inv);
+#pragma unroll
+        for (int m = 0; m < L; ++m) F[m + 1] = (R(2 * m + 1) * F[m] - e) * R(0.5) * inv;
+    }
+}
+
+// Hermite Coulomb integrals R_tuv for t+u+v <= L:
+// R^(n)_000 = (-2 alpha)^n F_n(T),
+// R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} + X R^(n+1)_{t,u,v}  (same for u with Y, v with Z).
+template <int L, typename R>
+__device__ __forceinline__ void hermite_R(R m2a, R X, R Y, R Z, const R (&F)[L + 1], R (&out)[L + 1][L + 1][L + 1])
+{
+    R pw[L + 1];
+    pw[0] = R(1);
+#pragma unroll
+    for (int n = 1; n <= L; n++) pw[n] = pw[n - 1] * m2a;
+    R cur[L + 1][L + 1][L + 1];
+    cur[0][0][0] = pw[L] * F[L];
+#pragma unroll
+    for (int n = L - 1; n >= 0; --n) {
+        R nxt[L + 1][L + 1][L + 1];
+#pragma unroll
+        for (int t = 0; t <= L; t++)
+#pragma unroll
+            for (int u = 0; u <= L; u++)
+#pragma unroll
+                for (int v = 0; v <= L; v++) {
+                    if (t + u + v > L - n) continue;
+                    R val;
+                    if (t + u + v == 0) val = pw[n] * F[n];
+                    else if (t > 0) val = (t > 1 ? R(t - 1) * cur[t > 1 ? t - 2 : 0][u][v] : R(0)) + X * cur[t - 1][u][v];
+                    else if (u > 0) val = (u > 1 ? R(u - 1) * cur[t][u > 1 ? u - 2 : 0][v] : R(0)) + Y * cur[t][u - 1][v];
+                    else val = (v > 1 ? R(v - 1) * cur[t][u][v > 1 ? v - 2 : 0] : R(0)) + Z * cur[t][u][v - 1];
+                    nxt[t][u][v] = val;
+                }
+#pragma unroll
+        for (int t = 0; t <= L; t++)
+#pragma unroll
+            for (int u = 0; u <= L; u++)
+#pragma unroll
+                for (int v = 0; v <= L; v++)
+                    if (t + u + v <= L - n) cur[t][u][v] = nxt[t][u][v];
+    }
+#pragma unroll
+    for (int t = 0; t <= L; t++)
+#pragma unroll
+        for (int u = 0; u <= L; u++)
+#pragma unroll
+            for (int v = 0; v <= L; v++)
+                if (t + u + v <= L) out[t][u][v] = cur[t][u][v];
+}
+
+// Hermite expansion coefficients of a 1D product x_A^i x_B^j (i, j <= 1):
+// e[combo][t], combo = i + 2 j:  E^00 = 1; E^10 = (XPA, 1/2p); E^01 = (XPB, 1/2p);
+// E^11 = (XPA XPB + 1/2p, (XPA + XPB)/2p, 1/4p^2).
+template <typename R>
+__device__ __forceinline__ void hermite_E(R XPA, R XPB, R i2p, R (&e)[4][3])
+{
+    e[0][0] = R(1); e[0][1] = R(0); e[0][2] = R(0);
+    e[1][0] = XPA; e[1][1] = i2p; e[1][2] = R(0);
+    e[2][0] = XPB; e[2][1] = i2p; e[2][2] = R(0);
+    e[3][0] = XPA * XPB + i2p; e[3][1] = (XPA + XPB) * i2p; e[3][2] = i2p * i2p;
+}
+
+// Cartesian exponent of component c (0..2 for p, s has 0) along direction d.
+__host__ __device__ constexpr int lexp(int L, int c, int d) { return (L == 1 && c == d) ? 1 : 0; }
+
+// ---------------------------------------------------------------------------
+// contracted shell quartet (ab|cd), McMurchie-Davidson:
+// (ab|cd) = 2 pi^(5/2) / (p q sqrt(p+q)) K_ab K_cd
+//           sum_tuv E^ab_tuv sum_tau,nu,phi (-1)^(tau+nu+phi) E^cd_tau,nu,phi R_{t+tau,u+nu,v+phi}
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int LC, int LD, typename R>
+__device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, const Shell& sc, const Shell& sd,
+                                            const PairPrim* __restrict__ ppb, const PairPrim* __restrict__ ppk,
+                                            const R* __restrict__ tab, R* acc)
+{
+    constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
+    constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
+    const R pi25 = R(2.0 * 17.493418327624862);   // 2 pi^(5/2)
+#pragma unroll
+    for (int i = 0; i < NA * NB * NC * ND; i++) acc[i] = R(0);
+    for (int ip = 0; ip < kNPrimPair; ip++) {
+        const PairPrim bp = ppb[ip];
+        const R p = R(bp.p), Kb = R(bp.K);
+        if (Kb == R(0)) continue;
+        R eb[3][4][3];
+        const R i2p = R(0.5) / p;
+#pragma unroll
+        for (int d = 0; d < 3; d++) hermite_E<R>(R(bp.P[d] - sa.A[d]), R(bp.P[d] - sb.A[d]), i2p, eb[d]);
+        for (int jp = 0; jp < kNPrimPair; jp++) {
+            const PairPrim kp = ppk[jp];
+            const R q = R(kp.p), Kk = R(kp.K);
+            if (Kk == R(0)) continue;
+            R ek[3][4][3];
+            const R i2q = R(0.5) / q;
+#pragma unroll
+            for (int d = 0; d < 3; d++) hermite_E<R>(R(kp.P[d] - sc.A[d]), R(kp.P[d] - sd.A[d]), i2q, ek[d]);
+            const R PQx = R(bp.P[0] - kp.P[0]), PQy = R(bp.P[1] - kp.P[1]), PQz = R(bp.P[2] - kp.P[2]);
+            const R pq = p + q, alpha = p * q / pq;
+            const R T = alpha * (PQx * PQx + PQy * PQy + PQz * PQz);
+            R F[L + 1];
+            boys<L, R>(T, F, tab);
+            R Rt[L + 1][L + 1][L + 1];
+            hermite_R<L, R>(R(-2) * alpha, PQx, PQy, PQz, F, Rt);
+            const R pref = pi25 / (p * q * sqrt(pq)) * Kb * Kk;
+#pragma unroll
+            for (int kc = 0; kc < NC; kc++)
+#pragma unroll
+                for (int ld = 0; ld < ND; ld++) {
+                    const int cx = lexp(LC, kc, 0) + 2 * lexp(LD, ld, 0);
+                    const int cy = lexp(LC, kc, 1) + 2 * lexp(LD, ld, 1);
+                    const int cz = lexp(LC, kc, 2) + 2 * lexp(LD, ld, 2);
+                    const int tx = lexp(LC, kc, 0) + lexp(LD, ld, 0);
+                    const int ty = lexp(LC, kc, 1) + lexp(LD, ld, 1);
+                    const int tz = lexp(LC, kc, 2) + lexp(LD, ld, 2);
+                    // H_tuv = sum (-1)^(tau+nu+phi) E^cd R_{t+tau,...} for t+u+v <= LAB
+                    R H[LAB + 1][LAB + 1][LAB + 1];
+#pragma unroll
+                    for (int t = 0; t <= LAB; t++)
+#pragma unroll
+                        for (int u = 0; u <= LAB; u++)
+#pragma unroll
+                            for (int v = 0; v <= LAB; v++) {
+                                if (t + u + v > LAB) continue;
+                                R h = R(0);
+#pragma unroll
+                                for (int ta = 0; ta <= 2; ta++)
+#pragma unroll
+                                    for (int nu = 0; nu <= 2; nu++)
+#pragma unroll
+                                        for (int ph = 0; ph <= 2; ph++) {
+                                            if (ta > tx || nu > ty || ph > tz) continue;
+                                            if (t + ta > L || u + nu > L || v + ph > L) continue;
+                                            if (t + ta + u + nu + v + ph > L) continue;
+                                            const R ee = ek[0][cx][ta] * ek[1][cy][nu] * ek[2][cz][ph];
+                                            const R rr = Rt[t + ta][u + nu][v + ph];
+                                            if ((ta + nu + ph) & 1) h -= ee * rr;
+                                            else h += ee * rr;
+                                        }
+                                H[t][u][v] = h;
+                            }
+#pragma unroll
+                    for (int ia = 0; ia < NA; ia++)
+#pragma unroll
+                        for (int jb = 0; jb < NB; jb++) {
+                            const int bx = lexp(LA, ia, 0) + 2 * lexp(LB, jb, 0);
+                            const int by = lexp(LA, ia, 1) + 2 * lexp(LB, jb, 1);
+                            const int bz = lexp(LA, ia, 2) + 2 * lexp(LB, jb, 2);
+                            const int sx = lexp(LA, ia, 0) + lexp(LB, jb, 0);
+                            const int sy = lexp(LA, ia, 1) + lexp(LB, jb, 1);
+                            const int sz = lexp(LA, ia, 2) + lexp(LB, jb, 2);
+                            R val = R(0);
+#pragma unroll
+                            for (int t = 0; t <= 2; t++)
+#pragma unroll
+                                for (int u = 0; u <= 2; u++)
+#pragma unroll
+                                    for (int v = 0; v <= 2; v++) {
+                                        if (t > sx || u > sy || v > sz || t + u + v > LAB) continue;
+                                        val += eb[0][bx][t] * eb[1][by][u] * eb[2][bz][v] * H[t][u][v];
+                                    }
+                            acc[((ia * NB + jb) * NC + kc) * ND + ld] += pref * val;
+                        }
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// quartet decoding shared by the ERI, J/K and unpack kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_mol(const long* __restrict__ off, int n, long q)
+{
+    int lo = 0, hi = n;  // off[lo] <= q < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void decode_quartet(int c, long q, int nket, int& i, int& j)
+{
+    if (class_tri(c)) {
+        long ii = (long)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+        while (ii * (ii + 1) / 2 > q) ii--;
+        while ((ii + 1) * (ii + 2) / 2 <= q) ii++;
+        i = (int)ii;
+        j = (int)(q - ii * (ii + 1) / 2);
+    } else {
+        i = (int)(q / nket);
+        j = (int)(q % nket);
+    }
+}
+
+struct EriArgs {
+    const MolDesc* mol;
+    const long* qoff;       // [n_mol + 1]
+    int n_mol;
+    long nq;                // quartets of this class in the batch
+    const Shell* shells;
+    const Pair* pb;         // bra pair class list
+    const Pair* pk;
+    const PairPrim* ppb;
+    const PairPrim* ppk;
+    const void* tab;
+    void* out;              // [ncomp][nq]
+};
+
+template <int LA, int LB, int LC, int LD, typename R, typename S>
+__global__ __launch_bounds__(128) void eri_class_kernel(EriArgs g)
+{
+    constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
+    constexpr int NCOMP = class_ncomp(C);
+    const long qg = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qg >= g.nq) return;
+    const int m = find_mol(g.qoff, g.n_mol, qg);
+    const MolDesc& md = g.mol[m];
+    const long q = qg - g.qoff[m];
+    int i, j;
+    decode_quartet(C, q, md.npair[class_ket(C)], i, j);
+    const int ib = md.pair0[class_bra(C)] + i, ik = md.pair0[class_ket(C)] + j;
+    const Pair P1 = g.pb[ib], P2 = g.pk[ik];
+    const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
+    R acc[NCOMP];
+    eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, g.ppb + (size_t)ib * kNPrimPair, g.ppk + (size_t)ik * kNPrimPair,
+                                   (const R*)g.tab, acc);
+    S* out = (S*)g.out;
+#pragma unroll
+    for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
+}
+
+// Primitive-pair tables of every shell pair of one pair class.
+__global__ void pair_kernel(const Shell* __restrict__ shells, const Pair* __restrict__ pairs, long npair,
+                            PairPrim* __restrict__ out)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npair * kNPrimPair) return;
+    const long ip = t / kNPrimPair;
+    const int k = (int)(t % kNPrimPair), ka = k / kNPrim, kb = k % kNPrim;
+    const Pair pr = pairs[ip];
+    const Shell& A = shells[pr.sa];
+    const Shell& B = shells[pr.sb];
+    const double a = A.a[ka], b = B.a[kb], p = a + b;
+    double r2 = 0.0;
+    PairPrim o;
+    o.p = p;
+    for (int d = 0; d < 3; d++) {
+        o.P[d] = (a * A.A[d] + b * B.A[d]) / p;
+        r2 += (A.A[d] - B.A[d]) * (A.A[d] - B.A[d]);
+    }
+    o.K = A.c[ka] * B.c[kb] * exp(-a * b / p * r2);
+    out[t] = o;
+}
+
+// ---------------------------------------------------------------------------
+// one-electron integrals (McMurchie-Davidson): one thread per AO pair
+// ---------------------------------------------------------------------------
+// 1D Hermite coefficients E^{ij}_t for i <= 1, j <= 3 by
+// E^{i,j+1}_t = E^{ij}_{t-1}/2p + XPB E^{ij}_t + (t+1) E^{ij}_{t+1} (same in i with XPA).
+__device__ inline void hermite_E_1e(double XPA, double XPB, double i2p, double (&E)[2][4][5])
+{
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 4; j++)
+            for (int t = 0; t < 5; t++) E[i][j][t] = 0.0;
+    E[0][0][0] = 1.0;
+    for (int j = 0; j < 3; j++)
+        for (int t = 0; t <= j + 1; t++)
+            E[0][j + 1][t] = (t > 0 ? i2p * E[0][j][t - 1] : 0.0) + XPB * E[0][j][t] + (t + 1 < 5 ? (t + 1) * E[0][j][t + 1] : 0.0);
+    for (int j = 0; j < 4; j++)
+        for (int t = 0; t <= j + 1 && t < 5; t++)
+            E[1][j][t] = (t > 0 ? i2p * E[0][j][t - 1] : 0.0) + XPA * E[0][j][t] + (t + 1 < 5 ? (t + 1) * E[0][j][t + 1] : 0.0);
+}
+
+__global__ void int1e_kernel(const MolDesc* __restrict__ mols, const Shell* __restrict__ shells,
+                             const int2* __restrict__ aoinfo, const double* __restrict__ Rat,
+                             const double* __restrict__ Zat, const double* __restrict__ tab,
+                             double* __restrict__ S, double* __restrict__ T, double* __restrict__ V,
+                             double* __restrict__ H)
+{
+    const int m = blockIdx.y;
+    const MolDesc md = mols[m];
+    const int N = md.nbf;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * (N + 1) / 2) return;
+    int mu = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (mu * (mu + 1) / 2 > t) mu--;
+    while ((mu + 1) * (mu + 2) / 2 <= t) mu++;
+    const int nu = t - mu * (mu + 1) / 2;
+    const int2 ia = aoinfo[md.ao0 + mu], ib = aoinfo[md.ao0 + nu];
+    const Shell& A = shells[ia.x];
+    const Shell& B = shells[ib.x];
+    int la[3], lb[3];
+    for (int d = 0; d < 3; d++) {
+        la[d] = lexp(A.L, ia.y, d);
+        lb[d] = lexp(B.L, ib.y, d);
+    }
+    double s = 0.0, kin = 0.0, v = 0.0;
+    for (int ka = 0; ka < kNPrim; ka++)
+        for (int kb = 0; kb < kNPrim; kb++) {
+            const double a = A.a[ka], b = B.a[kb], p = a + b, i2p = 0.5 / p;
+            double P[3], r2 = 0.0, E[3][2][4][5];
+            for (int d = 0; d < 3; d++) {
+                P[d] = (a * A.A[d] + b * B.A[d]) / p;
+                r2 += (A.A[d] - B.A[d]) * (A.A[d] - B.A[d]);
+                hermite_E_1e(P[d] - A.A[d], P[d] - B.A[d], i2p, E[d]);
+            }
+            const double K = A.c[ka] * B.c[kb] * exp(-a * b / p * r2);
+            const double sp = sqrt(kPi / p);
+            double Sd[3], Td[3];
+            for (int d = 0; d < 3; d++) {
+                const int i = la[d], j = lb[d];
+                Sd[d] = E[d][i][j][0] * sp;
+                // -1/2 d^2/dx^2 acting on x_B^j exp(-b x_B^2)
+                double t2 = 4.0 * b * b * E[d][i][j + 2][0] * sp - 2.0 * b * (2 * j + 1) * Sd[d];
+                if (j >= 2) t2 += j * (j - 1) * E[d][i][j - 2][0] * sp;
+                Td[d] = -0.5 * t2;
+            }
+            s += K * Sd[0] * Sd[1] * Sd[2];
+            kin += K * (Td[0] * Sd[1] * Sd[2] + Sd[0] * Td[1] * Sd[2] + Sd[0] * Sd[1] * Td[2]);
+            for (int c = 0; c < md.natom; c++) {
+                const double* Rc = Rat + 3 * (md.atom0 + c);
+                const double X = P[0] - Rc[0], Y = P[1] - Rc[1], Z = P[2] - Rc[2];
+                double F[3], Rt[3][3][3];
+                boys<2, double>(p * (X * X + Y * Y + Z * Z), F, tab);
+                hermite_R<2, double>(-2.0 * p, X, Y, Z, F, Rt);
+                double sum = 0.0;
+                for (int tt = 0; tt <= la[0] + lb[0]; tt++)
+                    for (int u = 0; u <= la[1] + lb[1]; u++)
+                        for (int w = 0; w <= la[2] + lb[2]; w++)
+                            sum += E[0][la[0]][lb[0]][tt] * E[1][la[1]][lb[1]][u] * E[2][la[2]][lb[2]][w] * Rt[tt][u][w];
+                v -= Zat[md.atom0 + c] * 2.0 * kPi / p * K * sum;
+            }
+        }
+    const long o = md.mat0;
+    S[o + mu * N + nu] = S[o + nu * N + mu] = s;
+    T[o + mu * N + nu] = T[o + nu * N + mu] = kin;
+    V[o + mu * N + nu] = V[o + nu * N + mu] = v;
+    H[o + mu * N + nu] = H[o + nu * N + mu] = kin + v;
+}
+
+// ---------------------------------------------------------------------------
+// packed unique-ERI copy-out of one molecule (canonical index of each component)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long pidx(int i, int j) { return i >= j ? (long)i * (i + 1) / 2 + j : (long)j * (j + 1) / 2 + i; }
+
+template <typename S>
+__global__ void eri_unpack_kernel(const MolDesc* __restrict__ mols, int m, int c, long nqc,
+                                  const Shell* __restrict__ shells, const Pair* __restrict__ pb,
+                                  const Pair* __restrict__ pk, const S* __restrict__ eri, double* __restrict__ out)
+{
+    const MolDesc md = mols[m];
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= md.nq[c]) return;
+    int i, j;
+    decode_quartet(c, q, md.npair[class_ket(c)], i, j);
+    const Pair P1 = pb[md.pair0[class_bra(c)] + i], P2 = pk[md.pair0[class_ket(c)] + j];
+    const Shell &A = shells[P1.sa], &B = shells[P1.sb], &Cc = shells[P2.sa], &D = shells[P2.sb];
+    const int na = A.L ? 3 : 1, nb = B.L ? 3 : 1, nc = Cc.L ? 3 : 1, nd = D.L ? 3 : 1;
+    const long qg = md.q0[c] + q;
+    int k = 0;
+    for (int ia = 0; ia < na; ia++)
+        for (int jb = 0; jb < nb; jb++)
+            for (int kc = 0; kc < nc; kc++)
+                for (int ld = 0; ld < nd; ld++, k++) {
+                    const long ij = pidx(A.ao + ia, B.ao + jb), kl = pidx(Cc.ao + kc, D.ao + ld);
+                    out[ij >= kl ? ij * (ij + 1) / 2 + kl : kl * (kl + 1) / 2 + ij] = (double)eri[(size_t)k * nqc + qg];
+                }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+ks_status launch_int1e(ks_batch* b)
+{
+    KTimer tm(b, "int1e");
+    int maxp = 0;
+    for (auto& m : b->mol) maxp = std::max(maxp, m.nbf * (m.nbf + 1) / 2);
+    dim3 grid((maxp + 127) / 128, b->n_mol);
+    hipLaunchKernelGGL(int1e_kernel, grid, dim3(128), 0, b->stream, b->d_mol, b->d_shells, b->d_aoinfo, b->d_R,
+                       b->d_Zc, b->d_boys, b->d_S, b->d_T, b->d_V, b->d_H);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+ks_status launch_pairs(ks_batch* b)
+{
+    for (int c = 0; c < 3; c++) {
+        long n = b->npairs[c] * kNPrimPair;
+        if (!n) continue;
+        hipLaunchKernelGGL(pair_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, b->d_shells,
+                           b->d_pairs[c], b->npairs[c], b->d_pp[c]);
+        KS_HIP(hipGetLastError());
+    }
+    return KS_OK;
+}
+
+template <int LA, int LB, int LC, int LD, typename R, typename S>
+static ks_status launch_class(ks_batch* b, int c)
+{
+    if (!b->nq[c]) return KS_OK;
+    EriArgs g;
+    g.mol = b->d_mol;
+    g.qoff = b->d_qoff[c];
+    g.n_mol = b->n_mol;
+    g.nq = b->nq[c];
+    g.shells = b->d_shells;
+    g.pb = b->d_pairs[class_bra(c)];
+    g.pk = b->d_pairs[class_ket(c)];
+    g.ppb = b->d_pp[class_bra(c)];
+    g.ppk = b->d_pp[class_ket(c)];
+    g.tab = std::is_same<R, double>::value ? (const void*)b->d_boys : (const void*)b->d_boys_f;
+    g.out = b->d_eri[c];
+    const long nb = (g.nq + 127) / 128;
+    hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S>), dim3((unsigned)nb), dim3(128), 0, b->stream, g);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+template <typename R, typename S>
+static ks_status launch_all_classes(ks_batch* b)
+{
+    ks_status st;
+    if ((st = launch_class<0, 0, 0, 0, R, S>(b, 0))) return st;
+    if ((st = launch_class<1, 0, 0, 0, R, S>(b, 1))) return st;
+    if ((st = launch_class<1, 0, 1, 0, R, S>(b, 2))) return st;
+    if ((st = launch_class<1, 1, 0, 0, R, S>(b, 3))) return st;
+    if ((st = launch_class<1, 1, 1, 0, R, S>(b, 4))) return st;
+    if ((st = launch_class<1, 1, 1, 1, R, S>(b, 5))) return st;
+    return KS_OK;
+}
+
+ks_status launch_eri(ks_batch* b)
+{
+    KTimer tm(b, "eri");
+    if (b->opt.prec == KS_MIXED) return launch_all_classes<double, float>(b);
+    return launch_all_classes<double, double>(b);
+}
+
+ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out)
+{
+    const MolDesc& md = b->mol[mol];
+    for (int c = 0; c < kNClass; c++) {
+        if (!md.nq[c]) continue;
+        const unsigned nb = (unsigned)((md.nq[c] + 127) / 128);
+        if (b->opt.prec == KS_MIXED)
+            hipLaunchKernelGGL(eri_unpack_kernel<float>, dim3(nb), dim3(128), 0, b->stream, b->d_mol, mol, c, b->nq[c],
+                               b->d_shells, b->d_pairs[class_bra(c)], b->d_pairs[class_ket(c)],
+                               (const float*)b->d_eri[c], d_out);
+        else
+            hipLaunchKernelGGL(eri_unpack_kernel<double>, dim3(nb), dim3(128), 0, b->stream, b->d_mol, mol, c, b->nq[c],
+                               b->d_shells, b->d_pairs[class_bra(c)], b->d_pairs[class_ket(c)],
+                               (const double*)b->d_eri[c], d_out);
+        KS_HIP(hipGetLastError());
+    }
+    return KS_OK;
+}
+
+}  // namespace ks

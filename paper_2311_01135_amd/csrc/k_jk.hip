@@ -1,0 +1,252 @@
+// J/K digestion of the packed unique ERIs against the density (paper
+// section 3.1: J_kl = sum_ij I_ijkl rho_ij, K_il = sum_jk I_ijkl rho_jk up to
+// the -1/2; section 3.2: the 8-fold symmetry cuts the digestion FLOPs 8x;
+// section 5 "Bottleneck": the ERIs act as a matrix M on x = flatten(rho)).
+//
+// Design for gfx950: one work group per (molecule, chunk of its quartets).
+// The density, J and K of that molecule sit in LDS (3 N^2 values, <= 160 KB),
+// the group streams its share of each class's ERIs from HBM (component-major,
+// so a wavefront reads contiguous 256 B rows), and each lane scatters the six
+// shell blocks J_ab, J_cd, K_ac, K_bc, K_ad, K_bd of its quartet with LDS
+// atomics.  For a unique shell quartet Q with stabiliser size s (a = b,
+// c = d and {ab} = {cd} each double it) summing all 8 permutations and
+// dividing by s gives the orbit sum, so per component
+//   AJ[ab] += 2/s I P_cd,  AJ[cd] += 2/s I P_ab,
+//   AK[ac] += 1/s I P_bd,  AK[bc] += 1/s I P_ad,  AK[ad] += 1/s I P_bc,  AK[bd] += 1/s I P_ac,
+// and J = AJ + AJ^T, K = AK + AK^T after the chunks are summed.  The
+// contraction is a matrix-vector product with no reuse dimension, so it runs
+// on VALU FMAs, bounded by the HBM stream of the integrals.
+#include "kernels.h"
+
+namespace ks {
+
+__device__ __forceinline__ void decode_quartet_jk(int c, long q, int nket, int& i, int& j)
+{
+    if (class_tri(c)) {
+        long ii = (long)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+        while (ii * (ii + 1) / 2 > q) ii--;
+        while ((ii + 1) * (ii + 2) / 2 <= q) ii++;
+        i = (int)ii;
+        j = (int)(q - ii * (ii + 1) / 2);
+    } else {
+        i = (int)(q / nket);
+        j = (int)(q % nket);
+    }
+}
+
+struct JkArgs {
+    const MolDesc* mol;
+    const MolState* state;
+    const JkItem* items;
+    const Shell* shells;
+    const Pair* pairs[3];
+    const void* eri[kNClass];
+    long nq[kNClass];
+    const double* P;
+    void* part;             // [items][2][np_max^2]
+    long part_stride;       // np_max^2
+    int only_active;
+};
+
+template <typename A>
+__device__ __forceinline__ void lds_add(A* p, A v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int LA, int LB, int LC, int LD, typename S, typename A>
+__device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md, int chunk, int nchunk,
+                                             const A* __restrict__ Ps, A* AJ, A* AK)
+{
+    constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
+    constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
+    constexpr int NCOMP = NA * NB * NC * ND;
+    const int N = md.nbf;
+    const long nq = md.nq[C];
+    const long lo = nq * chunk / nchunk, hi = nq * (chunk + 1) / nchunk;
+    const S* __restrict__ eri = (const S*)g.eri[C];
+    const long NQ = g.nq[C];
+    const Pair* pb = g.pairs[class_bra(C)];
+    const Pair* pk = g.pairs[class_ket(C)];
+    for (long q = lo + threadIdx.x; q < hi; q += blockDim.x) {
+        int i, j;
+        decode_quartet_jk(C, q, md.npair[class_ket(C)], i, j);
+        const Pair P1 = pb[md.pair0[class_bra(C)] + i], P2 = pk[md.pair0[class_ket(C)] + j];
+        const int oa = g.shells[P1.sa].ao, ob = g.shells[P1.sb].ao;
+        const int oc = g.shells[P2.sa].ao, od = g.shells[P2.sb].ao;
+        A f = A(1);
+        if (P1.sa == P1.sb) f *= A(0.5);
+        if (P2.sa == P2.sb) f *= A(0.5);
+        if (class_tri(C) && i == j) f *= A(0.5);
+        const long qg = md.q0[C] + q;
+        A I[NCOMP];
+#pragma unroll
+        for (int k = 0; k < NCOMP; k++) I[k] = A(eri[(size_t)k * NQ + qg]);
+        A pab[NA][NB], pcd[NC][ND], pbd[NB][ND], pbc[NB][NC], pad[NA][ND], pac[NA][NC];
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) pab[a][b] = Ps[(oa + a) * N + ob + b];
+#pragma unroll
+        for (int c = 0; c < NC; c++)
+#pragma unroll
+            for (int d = 0; d < ND; d++) pcd[c][d] = Ps[(oc + c) * N + od + d];
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+#pragma unroll
+            for (int d = 0; d < ND; d++) pbd[b][d] = Ps[(ob + b) * N + od + d];
+#pragma unroll
+            for (int c = 0; c < NC; c++) pbc[b][c] = Ps[(ob + b) * N + oc + c];
+        }
+#pragma unroll
+        for (int a = 0; a < NA; a++) {
+#pragma unroll
+            for (int d = 0; d < ND; d++) pad[a][d] = Ps[(oa + a) * N + od + d];
+#pragma unroll
+            for (int c = 0; c < NC; c++) pac[a][c] = Ps[(oa + a) * N + oc + c];
+        }
+        A jab[NA][NB] = {}, jcd[NC][ND] = {}, kac[NA][NC] = {}, kbc[NB][NC] = {}, kad[NA][ND] = {}, kbd[NB][ND] = {};
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+#pragma unroll
+                for (int c = 0; c < NC; c++)
+#pragma unroll
+                    for (int d = 0; d < ND; d++) {
+                        const A v = I[((a * NB + b) * NC + c) * ND + d];
+                        jab[a][b] += v * pcd[c][d];
+                        jcd[c][d] += v * pab[a][b];
+                        kac[a][c] += v * pbd[b][d];
+                        kbc[b][c] += v * pad[a][d];
+                        kad[a][d] += v * pbc[b][c];
+                        kbd[b][d] += v * pac[a][c];
+                    }
+        const A f2 = A(2) * f;
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[a][b]);
+#pragma unroll
+        for (int c = 0; c < NC; c++)
+#pragma unroll
+            for (int d = 0; d < ND; d++) lds_add(&AJ[(oc + c) * N + od + d], f2 * jcd[c][d]);
+#pragma unroll
+        for (int a = 0; a < NA; a++) {
+#pragma unroll
+            for (int c = 0; c < NC; c++) lds_add(&AK[(oa + a) * N + oc + c], f * kac[a][c]);
+#pragma unroll
+            for (int d = 0; d < ND; d++) lds_add(&AK[(oa + a) * N + od + d], f * kad[a][d]);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+#pragma unroll
+            for (int c = 0; c < NC; c++) lds_add(&AK[(ob + b) * N + oc + c], f * kbc[b][c]);
+#pragma unroll
+            for (int d = 0; d < ND; d++) lds_add(&AK[(ob + b) * N + od + d], f * kbd[b][d]);
+        }
+    }
+}
+
+template <typename S, typename A>
+__global__ __launch_bounds__(256) void jk_kernel(JkArgs g)
+{
+    const JkItem it = g.items[blockIdx.x];
+    if (g.only_active && g.state[it.mol].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = g.mol[it.mol];
+    const int N = md.nbf, NN = N * N;
+    extern __shared__ __align__(16) unsigned char smem_jk[];
+    A* Ps = (A*)smem_jk;
+    A* AJ = Ps + NN;
+    A* AK = AJ + NN;
+    const double* P = g.P + md.mat0;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        Ps[i] = A(P[i]);
+        AJ[i] = A(0);
+        AK[i] = A(0);
+    }
+    __syncthreads();
+    digest_class<0, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
+    digest_class<1, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
+    digest_class<1, 0, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
+    digest_class<1, 1, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
+    digest_class<1, 1, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
+    digest_class<1, 1, 1, 1, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
+    __syncthreads();
+    A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        out[i] = AJ[i];
+        out[g.part_stride + i] = AK[i];
+    }
+}
+
+// J = sum_chunks (AJ + AJ^T), K = sum_chunks (AK + AK^T), in FP64.
+template <typename A>
+__global__ void jk_reduce_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state, int nchunk,
+                                 const A* __restrict__ part, long stride, int only_active, double* __restrict__ J,
+                                 double* __restrict__ K)
+{
+    const int m = blockIdx.y;
+    if (only_active && state[m].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = mols[m];
+    const int N = md.nbf;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int mu = t / N, nu = t % N;
+    double sj = 0.0, sk = 0.0;
+    for (int c = 0; c < nchunk; c++) {
+        const A* pj = part + (size_t)(m * nchunk + c) * 2 * stride;
+        const A* pk = pj + stride;
+        sj += (double)pj[mu * N + nu] + (double)pj[nu * N + mu];
+        sk += (double)pk[mu * N + nu] + (double)pk[nu * N + mu];
+    }
+    J[md.mat0 + t] = sj;
+    K[md.mat0 + t] = sk;
+}
+
+size_t jk_lds_bytes(const ks_batch* b)
+{
+    const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
+    int maxn = 0;
+    for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
+    return 3 * (size_t)maxn * maxn * es;
+}
+
+template <typename S, typename A>
+static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active)
+{
+    JkArgs g;
+    g.mol = b->d_mol;
+    g.state = b->d_state;
+    g.items = b->d_jk_items;
+    g.shells = b->d_shells;
+    for (int c = 0; c < 3; c++) g.pairs[c] = b->d_pairs[c];
+    for (int c = 0; c < kNClass; c++) {
+        g.eri[c] = b->d_eri[c];
+        g.nq[c] = b->nq[c];
+    }
+    g.P = P;
+    g.part = b->d_jk_part;
+    g.part_stride = (long)b->max_np * b->max_np;
+    g.only_active = only_active;
+    const size_t lds = jk_lds_bytes(b);
+    KS_HIP(hipFuncSetAttribute((const void*)jk_kernel<S, A>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((jk_kernel<S, A>), dim3((unsigned)b->jk_items.size()), dim3(256), lds, b->stream, g);
+    KS_HIP(hipGetLastError());
+    const int nchunk = b->jk_items.empty() ? 1 : b->jk_items[0].nchunk;
+    int maxnn = 0;
+    for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
+    hipLaunchKernelGGL(jk_reduce_kernel<A>, dim3((maxnn + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
+                       b->d_state, nchunk, (const A*)b->d_jk_part, g.part_stride, (int)only_active, J, K);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active)
+{
+    KTimer tm(b, "jk");
+    if (b->opt.prec == KS_MIXED) return run_jk<float, float>(b, P, J, K, only_active);
+    return run_jk<double, double>(b, P, J, K, only_active);
+}
+
+}  // namespace ks

@@ -1,0 +1,498 @@
+// Becke-partitioned atom-centred grid and the fused exchange-correlation
+// integration (paper section 3.1: V_XC(rho); section 3.2 "Libxc": B3LYP in
+// float32; section 5 "Recomputation": AO values recomputed on the grid
+// instead of stored).
+//
+// Grid: per atom a Treutler-Ahlrichs M4 radial rule (xi = 1) x Gauss-Legendre
+// in cos(theta) x trapezoid in phi, weighted by Becke fuzzy-cell functions
+// (three smoothing steps, no size adjustment).
+//
+// XC: one work group (8 wavefronts) walks a contiguous chunk of one
+// molecule's grid in sub-blocks of BP points.  Per sub-block it evaluates the
+// AO values and gradients into LDS, forms X = Phi P with 16x16x4 MFMAs (P read
+// from L2), reduces rho = sum X Phi and grad rho = 2 sum X grad Phi per point,
+// evaluates B3LYP, forms W = w (v_rho/2 Phi + 2 v_sigma grad rho . grad Phi),
+// and accumulates A += Phi^T W with MFMAs into register tiles that persist over
+// the whole chunk.  V_XC = sum_chunks (A + A^T) is summed in FP64 afterwards.
+#include "kernels.h"
+
+namespace ks {
+
+// ---------------------------------------------------------------------------
+// grid points and Becke weights
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double becke_s(double mu)
+{
+#pragma unroll
+    for (int k = 0; k < 3; k++) mu = 1.5 * mu - 0.5 * mu * mu * mu;
+    return 0.5 * (1.0 - mu);
+}
+
+// blockIdx.y = molecule; each thread one of its points.  LDS: atom positions
+// and per-thread distances to every atom (transposed: [atom][thread]).
+__global__ __launch_bounds__(128) void grid_kernel(const MolDesc* __restrict__ mols, const double* __restrict__ Rat,
+                                                   const double* __restrict__ radial, const double* __restrict__ ang,
+                                                   int nrad, int nth, int nph, double* __restrict__ out)
+{
+    const int m = blockIdx.y;
+    const MolDesc md = mols[m];
+    const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ double smem_grid[];
+    double* Ra = smem_grid;                       // [natom][3]
+    double* dist = smem_grid + 3 * md.natom;     // [natom][blockDim]
+    for (int i = threadIdx.x; i < 3 * md.natom; i += blockDim.x) Ra[i] = Rat[3 * md.atom0 + i];
+    __syncthreads();
+    if (l >= md.ngrid) return;
+    const int per_atom = nrad * nth * nph;
+    const int A = (int)(l / per_atom);
+    int rem = (int)(l % per_atom);
+    const int i = rem / (nth * nph);
+    rem %= nth * nph;
+    const int j = rem / nph, k = rem % nph;
+    const double ct = ang[j], st = sqrt(1.0 - ct * ct), ph = 2.0 * kPi * k / nph;
+    const double r = radial[i];
+    double p[3];
+    p[0] = Ra[3 * A] + r * st * cos(ph);
+    p[1] = Ra[3 * A + 1] + r * st * sin(ph);
+    p[2] = Ra[3 * A + 2] + r * ct;
+    const int bs = blockDim.x, t = threadIdx.x;
+    for (int a = 0; a < md.natom; a++) {
+        const double dx = p[0] - Ra[3 * a], dy = p[1] - Ra[3 * a + 1], dz = p[2] - Ra[3 * a + 2];
+        dist[a * bs + t] = sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    double num = 0.0, den = 0.0;
+    for (int a = 0; a < md.natom; a++) {
+        const double ra = dist[a * bs + t];
+        double Pa = 1.0;
+        for (int c = 0; c < md.natom && Pa > 0.0; c++) {
+            if (c == a) continue;
+            const double dx = Ra[3 * a] - Ra[3 * c], dy = Ra[3 * a + 1] - Ra[3 * c + 1], dz = Ra[3 * a + 2] - Ra[3 * c + 2];
+            const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+            Pa *= becke_s((ra - dist[c * bs + t]) * inv);
+        }
+        if (a == A) num = Pa;
+        den += Pa;
+    }
+    const double w = radial[nrad + i] * ang[nth + j] * (2.0 * kPi / nph) * (num / den);
+    double* o = out + 4 * (md.grid0 + l);
+    o[0] = p[0];
+    o[1] = p[1];
+    o[2] = p[2];
+    o[3] = w;
+}
+
+ks_status launch_grid(ks_batch* b)
+{
+    KTimer tm(b, "grid");
+    long maxg = 0;
+    int maxat = 0;
+    for (auto& m : b->mol) {
+        maxg = std::max(maxg, m.ngrid);
+        maxat = std::max(maxat, m.natom);
+    }
+    const int bs = 128;
+    const size_t lds = sizeof(double) * (3 * maxat + (size_t)maxat * bs);
+    KS_HIP(hipFuncSetAttribute((const void*)grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, b->stream,
+                       b->d_mol, b->d_R, b->d_radial, b->d_ang, b->opt.n_rad, b->opt.n_theta, b->opt.n_phi, b->d_grid);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// B3LYP, closed shell: energy per volume e and v_rho = de/drho,
+// v_sigma = de/dsigma (sigma = |grad rho|^2).
+// e = 0.08 Slater + 0.72 B88 + 0.19 VWN + 0.81 LYP
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void b3lyp(F rho, F sigma, int vwn5, F& e, F& vr, F& vs)
+{
+    const F pi = F(kPi);
+    const F r13 = cbrt(rho);
+    // Slater exchange, -(3/4)(3/pi)^(1/3) rho^(4/3)
+    const F cs = F(0.7385587663820224);
+    const F eS = -cs * rho * r13;
+    const F vS = F(-4.0 / 3.0) * cs * r13;
+    // Becke 88, both spins: rho_s = rho/2, g_s = sqrt(sigma)/2, x = g_s / rho_s^(4/3)
+    const F beta = F(0.0042), Cx = F(0.9305257363491000);   // (3/2)(3/(4 pi))^(1/3)
+    const F rs13 = r13 * F(0.7937005259840998);               // (rho/2)^(1/3)
+    const F rs43 = F(0.5) * rho * rs13;
+    const F x = F(0.5) * sqrt(sigma) / rs43;
+    const F ash = asinh(x);
+    const F D = F(1) + F(6) * beta * x * ash;
+    const F Dp = F(6) * beta * (ash + x / sqrt(F(1) + x * x));
+    const F gx = x / D;                       // g(x)/x with g = x^2/D
+    const F gpx = (F(2) * D - x * Dp) / (D * D);   // g'(x)/x
+    const F eB = F(-2) * rs43 * (Cx + beta * x * gx);
+    const F vB = F(-4.0 / 3.0) * rs13 * (Cx + beta * x * (gx - x * gpx));
+    const F sB = -beta * gpx / (F(4) * rs43);
+    // VWN (paramagnetic), x_v = sqrt(r_s)
+    F b, c, x0;
+    if (vwn5) { b = F(3.72744); c = F(12.9352); x0 = F(-0.10498); }
+    else { b = F(13.0720); c = F(42.7198); x0 = F(-0.409286); }
+    const F Av = F(0.0310907);
+    const F rsv = cbrt(F(3) / (F(4) * pi * rho));
+    const F xv = sqrt(rsv);
+    const F X = xv * xv + b * xv + c, X0 = x0 * x0 + b * x0 + c, Q = sqrt(F(4) * c - b * b);
+    const F at = atan(Q / (F(2) * xv + b));
+    const F bxX0 = b * x0 / X0;
+    const F epsv = Av * (log(xv * xv / X) + F(2) * b / Q * at
+                         - bxX0 * (log((xv - x0) * (xv - x0) / X) + F(2) * (b + F(2) * x0) / Q * at));
+    const F deps = Av * (F(2) / xv - (F(2) * xv + b) / X - b / X
+                         - bxX0 * (F(2) / (xv - x0) - (F(2) * xv + b) / X - (b + F(2) * x0) / X));
+    const F eV = rho * epsv;
+    const F vV = epsv - xv * deps / F(6);
+    // LYP, closed-shell gradient form; t = rho^(-1/3)
+    const F la = F(0.04918), lb = F(0.132), lc = F(0.2533), ld = F(0.349);
+    const F CF = F(2.8712340001881915);      // (3/10)(3 pi^2)^(2/3)
+    const F t = F(1) / r13, den = F(1) + ld * t, Ee = exp(-lc * t) / den;
+    const F delta = lc * t + ld * t / den;
+    const F t5 = t * t * t * t * t;          // rho^(-5/3)
+    const F abE = la * lb * Ee;
+    const F eL = -la * rho / den - abE * CF * rho + abE / F(72) * t5 * sigma * (F(3) + F(7) * delta);
+    const F vL = -la / den - la * ld * t / (F(3) * den * den) - abE * CF * (F(1) + delta / F(3))
+                 + abE / F(72) * sigma * t5 / rho / F(3)
+                       * (F(7) * delta * delta - F(39) * delta - F(15) + F(7) * ld * ld * t * t / (den * den));
+    const F sL = abE / F(72) * t5 * (F(3) + F(7) * delta);
+    e = F(0.08) * eS + F(0.72) * eB + F(0.19) * eV + F(0.81) * eL;
+    vr = F(0.08) * vS + F(0.72) * vB + F(0.19) * vV + F(0.81) * vL;
+    vs = F(0.72) * sB + F(0.81) * sL;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA wrappers: A operand lane l holds A[l%16][l/16], B operand B[l/16][l%16];
+// output register r of lane l holds D[row(l, r)][l%16].
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4_t V;
+    static __device__ __forceinline__ V run(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+    typedef f4_t V;
+    static __device__ __forceinline__ V run(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+// padded copy of P in the compute type: Pt[m] is np x np, zero outside nbf.
+template <typename T>
+__global__ void pad_density_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state,
+                                   const long* __restrict__ ptoff, const double* __restrict__ P, T* __restrict__ Pt,
+                                   int only_active)
+{
+    const int m = blockIdx.y;
+    if (only_active && state[m].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = mols[m];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= md.np * md.np) return;
+    const int i = t / md.np, j = t % md.np;
+    Pt[ptoff[m] + t] = (i < md.nbf && j < md.nbf) ? (T)P[md.mat0 + i * md.nbf + j] : T(0);
+}
+
+struct XcArgs {
+    const MolDesc* mol;
+    const MolState* state;
+    const XcItem* items;
+    const Shell* shells;
+    const double* grid;
+    const void* Pt;
+    const long* ptoff;
+    void* part;             // [items][np_max^2]
+    double* part_exc;       // [items]
+    long part_stride;
+    int vwn5;
+    int only_active;
+};
+
+constexpr int kXcThreads = 512;
+constexpr int kXcWaves = kXcThreads / 64;
+
+template <typename T> struct XcBlock;
+template <> struct XcBlock<double> { static constexpr int BP = 32; };
+template <> struct XcBlock<float> { static constexpr int BP = 64; };
+
+template <typename T>
+__host__ __device__ constexpr size_t xc_lds_bytes_for(int np)
+{
+    return (size_t)5 * XcBlock<T>::BP * (np + 1) * sizeof(T) + (size_t)XcBlock<T>::BP * 4 * sizeof(double)
+           + (size_t)XcBlock<T>::BP * 4 * sizeof(T) + kXcWaves * sizeof(double) + 64;
+}
+
+template <typename T, int MAXT>
+__global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
+{
+    constexpr int BP = XcBlock<T>::BP;
+    constexpr int TPP = kXcThreads / BP;     // threads per point in the density reduction
+    typedef typename Mfma<T>::V V;
+    const XcItem it = g.items[blockIdx.x];
+    const int m = it.mol;
+    if (g.only_active && g.state[m].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = g.mol[m];
+    const int N = md.nbf, NP = md.np, NT = NP >> 4, LD = NP + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, l4 = lane >> 4;
+
+    extern __shared__ __align__(16) unsigned char smem_xc[];
+    double* pts = (double*)smem_xc;                          // [BP][4]
+    double* wsum = pts + BP * 4;                              // [waves]
+    T* coef = (T*)(wsum + kXcWaves);                          // [BP][4]
+    T* Phi = coef + BP * 4;                                   // [BP][LD]
+    T* dPhi = Phi + BP * LD;                                  // [3][BP][LD]
+    T* XW = dPhi + 3 * BP * LD;                               // [BP][LD]
+
+    const T* __restrict__ Pt = (const T*)g.Pt + g.ptoff[m];
+    const Shell* __restrict__ sh = g.shells + md.shell0;
+
+    for (int i = tid; i < 5 * BP * LD; i += kXcThreads) Phi[i] = T(0);
+
+    V acc[MAXT];
+#pragma unroll
+    for (int k = 0; k < MAXT; k++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) acc[k][r] = T(0);
+
+    double exc = 0.0, exc_c = 0.0;   // Neumaier pair, one per point-owner thread
+    const double far[3] = {sh[0].A[0] + 300.0, sh[0].A[1] + 300.0, sh[0].A[2] + 300.0};
+
+    for (long g0 = it.g0; g0 < it.g1; g0 += BP) {
+        __syncthreads();
+        if (tid < BP) {
+            const long gp = g0 + tid;
+            if (gp < it.g1) {
+                const double* src = g.grid + 4 * (md.grid0 + gp);
+                pts[4 * tid] = src[0];
+                pts[4 * tid + 1] = src[1];
+                pts[4 * tid + 2] = src[2];
+                pts[4 * tid + 3] = src[3];
+            } else {
+                pts[4 * tid] = far[0];
+                pts[4 * tid + 1] = far[1];
+                pts[4 * tid + 2] = far[2];
+                pts[4 * tid + 3] = 0.0;
+            }
+        }
+        __syncthreads();
+        // AO values and gradients: item = (point, shell), point fastest
+        for (int itx = tid; itx < BP * md.nshell; itx += kXcThreads) {
+            const int gi = itx % BP, s = itx / BP;
+            const Shell S = sh[s];
+            const T dx = (T)(pts[4 * gi] - S.A[0]), dy = (T)(pts[4 * gi + 1] - S.A[1]), dz = (T)(pts[4 * gi + 2] - S.A[2]);
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            T R = T(0), dR = T(0);
+#pragma unroll
+            for (int k = 0; k < kNPrim; k++) {
+                const T ar = (T)S.a[k] * r2;
+                if (ar < T(80)) {
+                    const T e = (T)S.c[k] * exp(-ar);
+                    R += e;
+                    dR -= T(2) * (T)S.a[k] * e;
+                }
+            }
+            const int mu = S.ao;
+            if (S.L == 0) {
+                Phi[gi * LD + mu] = R;
+                dPhi[gi * LD + mu] = dR * dx;
+                dPhi[(BP + gi) * LD + mu] = dR * dy;
+                dPhi[(2 * BP + gi) * LD + mu] = dR * dz;
+            } else {
+                const T d[3] = {dx, dy, dz};
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    Phi[gi * LD + mu + c] = d[c] * R;
+#pragma unroll
+                    for (int k = 0; k < 3; k++)
+                        dPhi[(k * BP + gi) * LD + mu + c] = (k == c ? R : T(0)) + d[c] * d[k] * dR;
+                }
+            }
+        }
+        __syncthreads();
+        // X = Phi P   (BP x NP) . (NP x NP)
+        for (int t = wave; t < (BP / 16) * NT; t += kXcWaves) {
+            const int gt = t / NT, nt = t % NT;
+            V c;
+#pragma unroll
+            for (int r = 0; r < 4; r++) c[r] = T(0);
+            for (int kk = 0; kk < NP; kk += 4) {
+                const T a = Phi[(gt * 16 + l16) * LD + kk + l4];
+                const T bb = Pt[(kk + l4) * NP + nt * 16 + l16];
+                c = Mfma<T>::run(a, bb, c);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) XW[(gt * 16 + Mfma<T>::row(lane, r)) * LD + nt * 16 + l16] = c[r];
+        }
+        __syncthreads();
+        // rho, grad rho per point; functional
+        {
+            const int gi = tid / TPP, sub = tid % TPP;
+            T r = T(0), gx = T(0), gy = T(0), gz = T(0);
+            for (int mu = sub; mu < N; mu += TPP) {
+                const T xv = XW[gi * LD + mu];
+                r += xv * Phi[gi * LD + mu];
+                gx += xv * dPhi[gi * LD + mu];
+                gy += xv * dPhi[(BP + gi) * LD + mu];
+                gz += xv * dPhi[(2 * BP + gi) * LD + mu];
+            }
+#pragma unroll
+            for (int o = TPP / 2; o >= 1; o >>= 1) {
+                r += __shfl_xor(r, o, TPP);
+                gx += __shfl_xor(gx, o, TPP);
+                gy += __shfl_xor(gy, o, TPP);
+                gz += __shfl_xor(gz, o, TPP);
+            }
+            if (sub == 0) {
+                const T w = (T)pts[4 * gi + 3];
+                gx *= T(2); gy *= T(2); gz *= T(2);
+                T c0 = T(0), c1 = T(0), c2 = T(0), c3 = T(0);
+                if (r >= T(kRhoCut) && w != T(0)) {
+                    T e, vr, vs;
+                    b3lyp<T>(r, gx * gx + gy * gy + gz * gz, g.vwn5, e, vr, vs);
+                    const double we = (double)w * (double)e;
+                    const double tt = exc + we;
+                    if (fabs(exc) >= fabs(we)) exc_c += (exc - tt) + we; else exc_c += (we - tt) + exc;
+                    exc = tt;
+                    c0 = T(0.5) * w * vr;
+                    const T s2 = T(2) * w * vs;
+                    c1 = s2 * gx; c2 = s2 * gy; c3 = s2 * gz;
+                }
+                coef[4 * gi] = c0; coef[4 * gi + 1] = c1; coef[4 * gi + 2] = c2; coef[4 * gi + 3] = c3;
+            }
+        }
+        __syncthreads();
+        // W = c0 Phi + c . grad Phi   (overwrites X)
+        for (int idx = tid; idx < BP * NP; idx += kXcThreads) {
+            const int gi = idx / NP, mu = idx % NP;
+            XW[gi * LD + mu] = coef[4 * gi] * Phi[gi * LD + mu] + coef[4 * gi + 1] * dPhi[gi * LD + mu]
+                             + coef[4 * gi + 2] * dPhi[(BP + gi) * LD + mu] + coef[4 * gi + 3] * dPhi[(2 * BP + gi) * LD + mu];
+        }
+        __syncthreads();
+        // A += Phi^T W   (NP x BP) . (BP x NP), tiles owned round-robin by wave
+#pragma unroll
+        for (int k = 0; k < MAXT; k++) {
+            const int t = wave + k * kXcWaves;
+            if (t < NT * NT) {
+                const int it2 = t / NT, jt = t % NT;
+                V c = acc[k];
+#pragma unroll 4
+                for (int kk = 0; kk < BP; kk += 4) {
+                    const T a = Phi[(kk + l4) * LD + it2 * 16 + l16];
+                    const T bb = XW[(kk + l4) * LD + jt * 16 + l16];
+                    c = Mfma<T>::run(a, bb, c);
+                }
+                acc[k] = c;
+            }
+        }
+    }
+    // write this chunk's A and E_xc
+    T* out = (T*)g.part + (size_t)blockIdx.x * g.part_stride;
+#pragma unroll
+    for (int k = 0; k < MAXT; k++) {
+        const int t = wave + k * kXcWaves;
+        if (t < NT * NT) {
+            const int it2 = t / NT, jt = t % NT;
+#pragma unroll
+            for (int r = 0; r < 4; r++) out[(it2 * 16 + Mfma<T>::row(lane, r)) * NP + jt * 16 + l16] = acc[k][r];
+        }
+    }
+    double tot = exc + exc_c;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    __syncthreads();
+    if (lane == 0) wsum[wave] = tot;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kXcWaves; w++) s += wsum[w];
+        g.part_exc[blockIdx.x] = s;
+    }
+}
+
+// V_XC = sum over the molecule's chunks of (A + A^T); E_XC = sum of chunk sums.
+template <typename T>
+__global__ void xc_reduce_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state,
+                                 const int* __restrict__ first, const T* __restrict__ part, long stride,
+                                 const double* __restrict__ part_exc, int only_active, double* __restrict__ V,
+                                 double* __restrict__ exc)
+{
+    const int m = blockIdx.y;
+    if (only_active && state[m].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = mols[m];
+    const int N = md.nbf, NP = md.np;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i0 = first[m], i1 = first[m + 1];
+    if (t == 0) {
+        double s = 0.0, c = 0.0;
+        for (int i = i0; i < i1; i++) {
+            const double x = part_exc[i], tt = s + x;
+            if (fabs(s) >= fabs(x)) c += (s - tt) + x; else c += (x - tt) + s;
+            s = tt;
+        }
+        exc[m] = s + c;
+    }
+    if (t >= N * N) return;
+    const int mu = t / N, nu = t % N;
+    double v = 0.0;
+    for (int i = i0; i < i1; i++) {
+        const T* p = part + (size_t)i * stride;
+        v += (double)p[mu * NP + nu] + (double)p[nu * NP + mu];
+    }
+    V[md.mat0 + t] = v;
+}
+
+template <typename T>
+static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_active)
+{
+    int maxnp2 = 0;
+    for (auto& m : b->mol) maxnp2 = std::max(maxnp2, m.np * m.np);
+    hipLaunchKernelGGL(pad_density_kernel<T>, dim3((maxnp2 + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
+                       b->d_state, b->d_ptoff, P, (T*)b->d_Pt, (int)only_active);
+    KS_HIP(hipGetLastError());
+    XcArgs g;
+    g.mol = b->d_mol;
+    g.state = b->d_state;
+    g.items = b->d_xc_items;
+    g.shells = b->d_shells;
+    g.grid = b->d_grid;
+    g.Pt = b->d_Pt;
+    g.ptoff = b->d_ptoff;
+    g.part = b->d_xc_part;
+    g.part_exc = b->d_xc_exc;
+    g.part_stride = (long)b->max_np * b->max_np;
+    g.vwn5 = b->opt.xc == KS_XC_B3LYP5;
+    g.only_active = only_active;
+    const size_t lds = xc_lds_bytes_for<T>(b->max_np);
+    const int nt = b->max_np / 16, maxt = (nt * nt + kXcWaves - 1) / kXcWaves;
+    const dim3 grid((unsigned)b->xc_items.size());
+    if (maxt <= 4) {
+        KS_HIP(hipFuncSetAttribute((const void*)xc_kernel<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((xc_kernel<T, 4>), grid, dim3(kXcThreads), lds, b->stream, g);
+    } else {
+        KS_HIP(hipFuncSetAttribute((const void*)xc_kernel<T, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((xc_kernel<T, 5>), grid, dim3(kXcThreads), lds, b->stream, g);
+    }
+    KS_HIP(hipGetLastError());
+    int maxnn = 0;
+    for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
+    hipLaunchKernelGGL(xc_reduce_kernel<T>, dim3((maxnn + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
+                       b->d_state, b->d_xc_first, (const T*)b->d_xc_part, g.part_stride, b->d_xc_exc,
+                       (int)only_active, V, b->d_exc);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active)
+{
+    KTimer tm(b, "xc");
+    if (b->opt.prec == KS_MIXED) return run_xc<float>(b, P, V, only_active);
+    return run_xc<double>(b, P, V, only_active);
+}
+
+size_t xc_lds_bytes(const ks_batch* b)
+{
+    return b->opt.prec == KS_MIXED ? xc_lds_bytes_for<float>(b->max_np) : xc_lds_bytes_for<double>(b->max_np);
+}
+
+}  // namespace ks

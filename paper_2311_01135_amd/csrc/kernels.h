@@ -1,0 +1,53 @@
+// Host-side launchers of the HIP kernels (one translation unit per family).
+#pragma once
+
+#include "ks_internal.h"
+
+namespace ks {
+
+// error plumbing
+void set_error(const char* fmt, ...);
+#define KS_HIP(x)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess) {                                                    \
+            ks::set_error("%s failed: %s (%s:%d)", #x, hipGetErrorString(e_),     \
+                          __FILE__, __LINE__);                                     \
+            return KS_EDEVICE;                                                     \
+        }                                                                          \
+    } while (0)
+
+// timing of kernel families (no-op unless b->timing)
+struct KTimer {
+    ks_batch* b;
+    const char* name;
+    hipEvent_t e0{}, e1{};
+    KTimer(ks_batch* b_, const char* n);
+    ~KTimer();
+};
+
+// integrals (k_ints.hip)
+void build_boys_table(std::vector<double>& tab);
+ks_status launch_int1e(ks_batch* b);
+ks_status launch_pairs(ks_batch* b);
+ks_status launch_eri(ks_batch* b);
+ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out);
+
+// J/K (k_jk.hip)
+ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active);
+size_t jk_lds_bytes(const ks_batch* b);
+
+// grid and XC (k_xc.hip)
+ks_status launch_grid(ks_batch* b);
+ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active);
+size_t xc_lds_bytes(const ks_batch* b);
+
+// SCF steps (k_scf.hip)
+ks_status launch_fock(ks_batch* b, const double* P, const double* J, const double* K, const double* Vxc,
+                      double* F, bool only_active, double* d_eterms);
+ks_status launch_lowdin(ks_batch* b);
+ks_status launch_guess(ks_batch* b);
+ks_status launch_iteration_tail(ks_batch* b);
+ks_status launch_count_active(ks_batch* b);
+
+}  // namespace ks

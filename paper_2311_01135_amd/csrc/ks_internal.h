@@ -1,0 +1,169 @@
+// Internal data layout of libks.so (shared by the host driver and the HIP
+// kernels; nothing here is part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ks.h"
+
+namespace ks {
+
+constexpr int kMaxNbf = 96;     // largest molecule the LDS-resident kernels take
+constexpr int kNPrim = 3;       // STO-3G: three primitives per shell
+constexpr int kNPrimPair = kNPrim * kNPrim;
+constexpr int kMaxDiis = 8;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kBohrAng = 0.52917721092;
+constexpr double kRhoCut = 1e-12;      // points below this density carry no XC
+
+// Boys-function table: F_m(T_i), T_i = i * kBoysDT, i < kBoysNT, m < kBoysM.
+constexpr double kBoysDT = 0.05;
+constexpr double kBoysTMax = 36.0;
+constexpr int kBoysNT = 722;
+constexpr int kBoysM = 12;
+
+// A contracted shell: 2s and 2p of a heavy atom are separate shells that
+// share exponents.  c[] already holds contraction x primitive normalisation
+// x contracted renormalisation.
+struct Shell {
+    double A[3];
+    double a[kNPrim];
+    double c[kNPrim];
+    int L;      // 0 = s, 1 = p
+    int ao;     // first AO index inside its molecule
+    int atom;   // atom index inside its molecule
+    int pad;
+};
+
+// Primitive-pair data of a shell pair (McMurchie-Davidson Gaussian product):
+// p = a + b, P = (a A + b B)/p, K = c_a c_b exp(-a b/p |A-B|^2).
+struct PairPrim {
+    double p, P[3], K;
+};
+
+// Shell pair (global shell indices); sa carries the higher angular momentum.
+struct Pair {
+    int sa, sb;
+};
+
+// Quartet classes (bra pair class, ket pair class), pair classes ss=0, ps=1, pp=2.
+constexpr int kNClass = 6;
+__host__ __device__ constexpr int class_bra(int c) { return c == 0 ? 0 : (c <= 2 ? 1 : 2); }
+__host__ __device__ constexpr int class_ket(int c) { return (c == 0 || c == 1 || c == 3) ? 0 : (c == 2 || c == 4 ? 1 : 2); }
+__host__ __device__ constexpr bool class_tri(int c) { return c == 0 || c == 2 || c == 5; }
+__host__ __device__ constexpr int class_ncomp(int c)
+{
+    return c == 0 ? 1 : (c == 1 ? 3 : (c == 2 || c == 3 ? 9 : (c == 4 ? 27 : 81)));
+}
+
+struct MolDesc {
+    int natom, nbf, nocc, nshell;
+    int atom0, shell0;      // offsets into the batch atom / shell arrays
+    int np;                 // nbf rounded up to 16
+    int ao0;                // first AO of this molecule in the batch AO table
+    long mat0;              // element offset of this molecule's N x N blocks
+    long grid0;             // first grid point
+    long ngrid;
+    int pair0[3];           // first pair of each pair class in the class lists
+    int npair[3];
+    long q0[kNClass];       // first quartet of each class in the batch-global class list
+    long nq[kNClass];
+    double enuc;
+};
+
+// Per-molecule SCF state kept on the device.
+struct MolState {
+    int status;             // KS_MOL_*
+    int iter;
+    int nhist;              // DIIS vectors held
+    int head;               // DIIS ring position
+    int final_;             // set when this iteration's F is the last one
+    int pad[3];
+    double E, Eprev, err;
+    double Eterms[6];
+    double B[kMaxDiis * kMaxDiis];   // DIIS overlaps of the held error vectors
+};
+
+// XC work item: a contiguous range of one molecule's grid points.
+struct XcItem {
+    int mol;
+    int pad;
+    long g0, g1;
+};
+
+struct JkItem {
+    int mol, chunk, nchunk, pad;
+};
+
+}  // namespace ks
+
+// ---------------------------------------------------------------------------
+// host-side batch
+// ---------------------------------------------------------------------------
+struct ks_batch {
+    ks_options opt;
+    hipStream_t stream = nullptr;
+    int n_mol = 0;
+    int max_np = 0;
+    double a0 = 0.2;
+    std::vector<ks::MolDesc> mol;
+    std::vector<ks::Shell> shells;
+    std::vector<int> Z;
+    std::vector<double> R;          // bohr
+    long nmat = 0;                  // sum nbf^2
+    long ngrid = 0;
+    long npairs[3] = {0, 0, 0};
+    long nq[ks::kNClass] = {0, 0, 0, 0, 0, 0};
+    long nprimq = 0;
+
+    // device memory (owned)
+    std::vector<void*> allocs;
+    ks::MolDesc* d_mol = nullptr;
+    ks::MolState* d_state = nullptr;
+    ks::Shell* d_shells = nullptr;
+    int2* d_aoinfo = nullptr;       // per batch AO: (global shell, component 0..2)
+    double* d_R = nullptr;          // atom positions (bohr)
+    double* d_Zc = nullptr;         // atom charges
+    ks::Pair* d_pairs[3] = {nullptr, nullptr, nullptr};
+    ks::PairPrim* d_pp[3] = {nullptr, nullptr, nullptr};
+    long* d_qoff[ks::kNClass] = {};  // prefix over molecules (n_mol + 1)
+    void* d_eri[ks::kNClass] = {};   // component-major, FP64 or FP32
+    double* d_boys = nullptr;
+    float* d_boys_f = nullptr;
+    double* d_radial = nullptr;     // r_i, w_i (n_rad each)
+    double* d_ang = nullptr;        // cos theta_j, w_j (n_theta each)
+    double* d_grid = nullptr;       // [ngrid][4]
+    // matrices (nmat doubles each)
+    double *d_S = nullptr, *d_T = nullptr, *d_V = nullptr, *d_H = nullptr, *d_X = nullptr;
+    double *d_F = nullptr, *d_P = nullptr, *d_J = nullptr, *d_K = nullptr, *d_Vxc = nullptr;
+    double *d_Fp = nullptr, *d_C = nullptr, *d_eps = nullptr, *d_work = nullptr;
+    double *d_Fh = nullptr, *d_Eh = nullptr;    // DIIS history (diis_space * nmat each)
+    void* d_Pt = nullptr;           // padded density in the XC compute type (np^2 per molecule)
+    long* d_ptoff = nullptr;        // offsets of d_Pt blocks
+    long npt_total = 0;
+    // J/K work
+    std::vector<ks::JkItem> jk_items;
+    ks::JkItem* d_jk_items = nullptr;
+    void* d_jk_part = nullptr;      // [items][2][kMaxNbf^2]
+    // XC work
+    std::vector<ks::XcItem> xc_items;
+    ks::XcItem* d_xc_items = nullptr;
+    int* d_xc_first = nullptr;      // [n_mol + 1] first XC item of each molecule
+    void* d_xc_part = nullptr;      // [items][np^2 max]
+    double* d_xc_exc = nullptr;     // [items]
+    double* d_exc = nullptr;        // [n_mol]
+    double* d_eterms = nullptr;     // [n_mol][6] energy terms of fock_build
+    int* d_nactive = nullptr;
+    int* h_nactive = nullptr;       // pinned
+
+    bool setup_done = false, eri_done = false, guess_done = false;
+    int iter = 0;
+
+    bool timing = false;
+    std::vector<std::string> tnames;
+    std::vector<double> tms;
+};

@@ -1,0 +1,219 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (FP64 path): one-electron integrals 1e-12, ERIs 1e-12 absolute,
+J/K 1e-11, grid weights 1e-12 relative, V_xc 1e-10, E_xc 1e-10; SCF: |dE| <=
+1e-8 Ha, max|dP| <= 1e-6, |d gap| <= 1e-8 Ha.  Mixed path: |dE|, |d gap| <=
+1e-4 Ha against the FP64 oracle.
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2311_01135_amd import molgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_01135_amd import ks as K
+    K.load()
+    return K
+
+
+def _mols_small():
+    # water, and trees with 1..3 heavy atoms: several shells of every class,
+    # uneven sizes in one batch
+    out = [molgen.water(0)]
+    for n, idx in ((1, 0), (2, 1), (3, 2)):
+        out.append(molgen.tree(n, 7, idx))
+    return out
+
+
+@pytest.fixture(scope="module")
+def small(ks):
+    mols = _mols_small()
+    orc = [O.Mol(z, x) for z, x in mols]
+    b = ks.Batch(mols)
+    b.setup()
+    b.eri_build()
+    yield mols, orc, b
+    b.close()
+
+
+def test_sizes(small):
+    mols, orc, b = small
+    for m, o in enumerate(orc):
+        assert b.nbf[m] == o.nbf and b.nocc[m] == o.nocc
+        assert b.n_eri[m] == o.n_eri()
+
+
+def test_one_electron(small):
+    mols, orc, b = small
+    for m, o in enumerate(orc):
+        S, T, V = o.int1e()
+        assert np.abs(b.matrix(m, "S") - S).max() < 1e-12
+        assert np.abs(b.matrix(m, "T") - T).max() < 1e-11
+        assert np.abs(b.matrix(m, "V") - V).max() < 1e-11
+
+
+def test_lowdin(small):
+    mols, orc, b = small
+    for m, o in enumerate(orc):
+        S, _, _ = o.int1e()
+        X = b.matrix(m, "X")
+        assert np.abs(X @ S @ X - np.eye(o.nbf)).max() < 1e-11
+        assert np.abs(X - X.T).max() < 1e-12
+
+
+def test_eri_packed(small):
+    mols, orc, b = small
+    for m, o in enumerate(orc):
+        ref = o.eri()
+        got = b.eri(m)
+        assert np.abs(got - ref).max() < 1e-12, m
+
+
+def test_grid(small):
+    mols, orc, b = small
+    for m, o in enumerate(orc):
+        ref = o.grid()
+        got = b.grid(m)
+        assert np.abs(got[:, :3] - ref[:, :3]).max() < 1e-12
+        assert np.abs(got[:, 3] - ref[:, 3]).max() <= 1e-12 * np.abs(ref[:, 3]).max()
+
+
+def _rand_density(o, seed):
+    # a symmetric density-like matrix: 2 C C^T of random orthonormal-ish orbitals
+    rng = np.random.default_rng(seed)
+    S, _, _ = o.int1e()
+    w, U = np.linalg.eigh(S)
+    X = U @ np.diag(w ** -0.5) @ U.T
+    Q, _ = np.linalg.qr(rng.standard_normal((o.nbf, o.nbf)))
+    C = X @ Q[:, :o.nocc]
+    return 2 * C @ C.T
+
+
+def test_jk(small, ks):
+    mols, orc, b = small
+    Ps = [_rand_density(o, 10 + m) for m, o in enumerate(orc)]
+    P = b.pack(Ps)
+    J, K = b.empty(), b.empty()
+    b.jk_build(P, J, K)
+    Js, Ks = b.unpack(J), b.unpack(K)
+    for m, o in enumerate(orc):
+        Jr, Kr = o.jk(o.eri(), Ps[m])
+        assert np.abs(Js[m] - Jr).max() < 1e-11, m
+        assert np.abs(Ks[m] - Kr).max() < 1e-11, m
+
+
+def test_xc(small, ks):
+    mols, orc, b = small
+    Ps = [_rand_density(o, 20 + m) for m, o in enumerate(orc)]
+    P = b.pack(Ps)
+    V = b.empty()
+    exc = b.xc_build(P, V)
+    Vs = b.unpack(V)
+    for m, o in enumerate(orc):
+        er, Vr = o.xc(O.XC_B3LYP, o.grid(), Ps[m])
+        assert abs(exc[m] - er) < 1e-10, (m, exc[m], er)
+        assert np.abs(Vs[m] - Vr).max() < 1e-10, m
+
+
+def test_fock_energy_terms(small, ks):
+    mols, orc, b = small
+    Ps = [_rand_density(o, 30 + m) for m, o in enumerate(orc)]
+    P = b.pack(Ps)
+    F = b.empty()
+    et = b.fock_build(P, F)
+    Fs = b.unpack(F)
+    for m, o in enumerate(orc):
+        S, T, V = o.int1e()
+        H = T + V
+        J, K = o.jk(o.eri(), Ps[m])
+        exc, Vx = o.xc(O.XC_B3LYP, o.grid(), Ps[m])
+        Fr = H + J - 0.1 * K + Vx
+        assert np.abs(Fs[m] - Fr).max() < 1e-10
+        ref = [np.sum(Ps[m] * H), 0.5 * np.sum(Ps[m] * J), -0.05 * np.sum(Ps[m] * K), exc, o.enuc()]
+        ref.append(sum(ref))
+        assert np.allclose(et[m], ref, rtol=0, atol=1e-9), (et[m], ref)
+
+
+def _oracle_scf(args):
+    z, x, kw = args
+    return O.Mol(z, x).scf(**kw)
+
+
+def _compare_scf(r, ref, tolE, tolP, tolgap):
+    assert r["status"] == 1 and ref["status"] == 1
+    assert abs(r["E"] - ref["E"]) <= tolE, (r["E"], ref["E"])
+    assert abs(r["gap"] - ref["gap"]) <= tolgap, (r["gap"], ref["gap"])
+    if tolP is not None:
+        assert np.abs(r["P"] - ref["P"]).max() <= tolP
+    assert abs(r["n_iter"] - ref["n_iter"]) <= 1
+
+
+@pytest.mark.parametrize("xc", [O.XC_HF, O.XC_B3LYP, O.XC_B3LYP5])
+def test_scf_fp64_small_batch(ks, xc):
+    mols = _mols_small()
+    with cf.ThreadPoolExecutor(4) as ex:
+        refs = list(ex.map(_oracle_scf, [(z, x, dict(xc=xc)) for z, x in mols]))
+    with ks.Batch(mols, xc=xc) as b:
+        b.scf_solve()
+        for m in range(len(mols)):
+            _compare_scf(b.result(m), refs[m], 1e-8, 1e-6, 1e-8)
+
+
+def test_scf_mixed_small_batch(ks):
+    mols = _mols_small()
+    with cf.ThreadPoolExecutor(4) as ex:
+        refs = list(ex.map(_oracle_scf, [(z, x, dict(xc=O.XC_B3LYP)) for z, x in mols]))
+    with ks.Batch(mols, prec=ks.KS_MIXED) as b:
+        b.scf_solve()
+        for m in range(len(mols)):
+            _compare_scf(b.result(m), refs[m], 1e-4, None, 1e-4)
+
+
+def test_batch_invariance(ks):
+    """A molecule's result alone equals its result inside a mixed batch."""
+    mols = _mols_small()
+    with ks.Batch([mols[2]]) as b1:
+        b1.scf_solve()
+        alone = b1.result(0)
+    with ks.Batch(mols) as b2:
+        b2.scf_solve()
+        mixed = b2.result(2)
+    assert abs(alone["E"] - mixed["E"]) < 1e-10
+    assert np.abs(alone["P"] - mixed["P"]).max() < 1e-8
+    assert alone["n_iter"] == mixed["n_iter"]
+
+
+def test_empty_work_and_maxiter(ks):
+    """max_iter = 1 retires every molecule as MAXITER after one Fock build."""
+    with ks.Batch([molgen.water(5)], max_iter=1) as b:
+        b.scf_solve()
+        r = b.result(0)
+        assert r["status"] == ks.MOL_MAXITER and r["n_iter"] == 1
+
+
+def test_eri_sampled_full_size(ks):
+    """9-heavy-atom molecule at full size: 3000 sampled ERIs vs single oracle evaluations."""
+    z, x = molgen.tree(9, 1, 0)
+    o = O.Mol(z, x)
+    with ks.Batch([(z, x)]) as b:
+        b.eri_build()
+        eri = b.eri(0)
+    rng = np.random.default_rng(5)
+    N = o.nbf
+    for _ in range(3000):
+        i, j, k, l = (int(v) for v in rng.integers(0, N, 4))
+        ij = i * (i + 1) // 2 + j if i >= j else j * (j + 1) // 2 + i
+        kl = k * (k + 1) // 2 + l if k >= l else l * (l + 1) // 2 + k
+        idx = ij * (ij + 1) // 2 + kl if ij >= kl else kl * (kl + 1) // 2 + ij
+        assert abs(eri[idx] - o.eri_one(i, j, k, l)) < 1e-12
