@@ -77,10 +77,20 @@ typedef struct {
     int diis_space;         /* <= 8 */
     int jk_chunks;          /* work groups per molecule for J/K (0 = automatic) */
     int xc_chunks;          /* work groups per molecule for XC (0 = automatic) */
+    int guess;              /* initial density: KS_GUESS_ATOM or KS_GUESS_CORE */
 } ks_options;
 
+/* Initial density.  The paper only says C_1 is initialised (section 3.1).
+ * KS_GUESS_ATOM: diagonal superposition of neutral-atom occupations (H 1s 1;
+ * C/N/O/F 1s 2, 2s 2, 2p (Z-4)/3 each) scaled to the electron count, used as
+ * the first density.  KS_GUESS_CORE: orbitals of the core Hamiltonian. */
+#define KS_GUESS_ATOM 0
+#define KS_GUESS_CORE 1
+
 /* Fills *o with the defaults: B3LYP, FP64, 50 x 12 x 24 grid, e_tol 1e-9,
- * comm_tol 1e-7, max_iter 100, diis_space 8, automatic chunking. */
+ * comm_tol 1e-7, max_iter 100, diis_space 8, automatic chunking, atomic
+ * guess.  With KS_MIXED the library raises e_tol to at least 1e-6 and
+ * comm_tol to at least 1e-5, the resolution of an FP32 Fock matrix. */
 void ks_default_options(ks_options* o);
 
 typedef struct ks_batch ks_batch;
@@ -162,11 +172,20 @@ ks_status ks_get_matrix(const ks_batch* b, int mol, int which, double* out);
 /* Grid points (x, y, z, w) in bohr of molecule mol: out[n_grid*4]. */
 ks_status ks_get_grid(const ks_batch* b, int mol, double* out);
 
-/* Average device time in milliseconds of the last launch of each kernel
- * family, measured with HIP events on the batch stream when timing is on
- * (ks_set_timing).  names/values arrays of length cap; returns count. */
-int ks_kernel_times(const ks_batch* b, const char** names, double* ms, int cap);
+/* Convergence monitor of molecule mol after the last scf_step: the energy of
+ * the last Fock build, its change from the previous iteration and the max
+ * norm of the orthogonalised commutator X^T (FPS - SPF) X. */
+ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, double* err);
+
+/* Kernel timing.  ks_set_timing(b, 1) clears the counters and records a pair
+ * of HIP events on the batch stream around every launch of each kernel
+ * family ("eri", "jk", "xc", ...) without host synchronisation;
+ * ks_kernel_times() waits for the recorded events and returns, per family,
+ * the average device milliseconds per launch (names/ms arrays of length cap;
+ * returns the number of families); ks_kernel_counts() the launch counts. */
 void ks_set_timing(ks_batch* b, int on);
+int ks_kernel_times(const ks_batch* b, const char** names, double* ms, int cap);
+int ks_kernel_counts(const ks_batch* b, double* launches, int cap);
 
 /* Releases the batch and all of its device memory.  NULL-safe. */
 void ks_batch_destroy(ks_batch* b);

@@ -1055,7 +1055,8 @@ static int diis_solve(int n, const double *B, double *c)
 /* Restricted Kohn-Sham SCF (paper section 3.1: iteration 0 precomputes
  * V, T, S, ERIs and the initial orbitals; iteration i forms rho_i, V_XC,
  * J, K and solves the generalised eigenproblem).
- *   X = S^-1/2 (Loewdin); guess: diagonalise X^T H X; P = 2 C_occ C_occ^T.
+ *   X = S^-1/2 (Loewdin); initial density: atomic occupations (guess 0) or
+ *   diagonalise X^T H X (guess 1); P = 2 C_occ C_occ^T.
  *   iteration k: F_k = H + J[P] - (a0/2) K[P] + V_xc[P],
  *     E_k = tr(PH) + 1/2 tr(PJ) - a0/4 tr(PK) + E_xc + E_nn,
  *     e_k = X^T (F P S - S P F) X;  converged when k > 1,
@@ -1066,7 +1067,7 @@ static int diis_solve(int n, const double *B, double *c)
  *   is the density that produced F_k.
  * Eterms[6] = {tr PH, 1/2 tr PJ, -a0/4 tr PK, E_xc, E_nn, E}. */
 int orc_scf(void *h, int xc, int nrad, int nth, int nph, double e_tol, double comm_tol,
-            int max_iter, int diis_space, double *E_out, double *eps, double *P_out,
+            int max_iter, int diis_space, int guess, double *E_out, double *eps, double *P_out,
             int *niter, int *status, double *Eterms)
 {
     omol *m = (omol *)h;
@@ -1099,9 +1100,26 @@ int orc_scf(void *h, int xc, int nrad, int nth, int nph, double e_tol, double co
             for (k = 0; k < N; k++) s += Cp[i * N + k] / sqrt(w[k]) * Cp[j * N + k];
             X[i * N + j] = s;
         }
-    /* core guess */
+    /* initial density (the paper's "initialise C_1" leaves the choice open):
+     * guess 0: diagonal superposition of neutral-atom ground-state
+     * occupations (H 1s 1; C/N/O/F 1s 2, 2s 2, 2p (Z-4)/3 each), scaled to
+     * N_e, used as rho_1 directly;  guess 1: core Hamiltonian -- diagonalise
+     * X^T H X at iteration 0. */
     memcpy(F, H, sizeof(double) * NN);
-    for (it = 0; it <= max_iter; it++) {
+    it = 0;
+    if (guess == 0) {
+        double tot = 0.0;
+        for (i = 0; i < m->nshell; i++) {
+            const oshell *s = &m->sh[i];
+            int Z = m->Z[s->atom], c;
+            double occ = (Z == 1) ? 1.0 : (s->L == 1 ? (Z - 4) / 3.0 : 2.0);
+            for (c = 0; c < (s->L ? 3 : 1); c++) P[(s->bf0 + c) * N + s->bf0 + c] = occ;
+        }
+        for (i = 0; i < N; i++) tot += P[i * N + i];
+        for (i = 0; i < N; i++) P[i * N + i] *= m->nelec / tot;
+        it = 1;
+    }
+    for (; it <= max_iter; it++) {
         if (it > 0) {
             ksum e1 = {0, 0}, e2 = {0, 0}, e3 = {0, 0};
             double exc = 0.0;

@@ -18,6 +18,7 @@ _LIB = os.path.join(_HERE, "libks_oracle.so")
 
 XC_HF, XC_B3LYP, XC_B3LYP5 = 0, 1, 2
 ST_CONVERGED, ST_MAXITER, ST_DIVERGED, ST_INVALID = 1, 2, 3, 4
+GUESS_ATOM, GUESS_CORE = 0, 1
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -66,7 +67,7 @@ def lib():
         L.orc_xc.argtypes = [C.c_void_p, C.c_int, C.c_long, _dp, _dp, _dp]
         L.orc_eigh.argtypes = [C.c_int, _dp, _dp, _dp]
         L.orc_scf.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
-                              C.c_int, C.c_int, C.POINTER(C.c_double), _dp, _dp,
+                              C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), _dp, _dp,
                               C.POINTER(C.c_int), C.POINTER(C.c_int), _dp]
         _lib = L
     return _lib
@@ -178,12 +179,12 @@ class Mol:
         return e, V
 
     def scf(self, xc: int = XC_B3LYP, nrad=50, nth=12, nph=24, e_tol=1e-9, comm_tol=1e-7,
-            max_iter=100, diis_space=8):
+            max_iter=100, diis_space=8, guess=GUESS_ATOM):
         N = self.nbf
         E = C.c_double()
         eps, P, terms = np.zeros(N), np.zeros((N, N)), np.zeros(6)
         nit, st = C.c_int(), C.c_int()
-        rc = lib().orc_scf(self.h, xc, nrad, nth, nph, e_tol, comm_tol, max_iter, diis_space,
+        rc = lib().orc_scf(self.h, xc, nrad, nth, nph, e_tol, comm_tol, max_iter, diis_space, guess,
                            C.byref(E), eps, P, C.byref(nit), C.byref(st), terms)
         if rc != 0:
             raise ValueError("oracle SCF failed: near-singular overlap")

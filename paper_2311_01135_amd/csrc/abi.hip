@@ -33,24 +33,36 @@ KTimer::KTimer(ks_batch* b_, const char* n) : b(b_), name(n)
     }
 }
 
+// Events are recorded on the batch stream around each launch and read back
+// lazily (resolve_timers), so timing adds no host synchronisation.
 KTimer::~KTimer()
 {
     if (!b->timing) return;
     (void)hipEventRecord(e1, b->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    int idx = -1;
     for (size_t i = 0; i < b->tnames.size(); i++)
-        if (b->tnames[i] == name) {
-            b->tms[2 * i] += ms;
-            b->tms[2 * i + 1] += 1.0;
-            return;
-        }
-    b->tnames.push_back(name);
-    b->tms.push_back(ms);
-    b->tms.push_back(1.0);
+        if (b->tnames[i] == name) idx = (int)i;
+    if (idx < 0) {
+        idx = (int)b->tnames.size();
+        b->tnames.push_back(name);
+        b->tms.push_back(0.0);
+        b->tms.push_back(0.0);
+    }
+    b->pending.push_back(ks_batch::Pending{idx, e0, e1});
+}
+
+void resolve_timers(ks_batch* b)
+{
+    for (auto& p : b->pending) {
+        (void)hipEventSynchronize(p.e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.e0, p.e1);
+        b->tms[2 * p.name] += ms;
+        b->tms[2 * p.name + 1] += 1.0;
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    b->pending.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -182,6 +194,7 @@ static ks_status upload(ks_batch* b, T** p, const std::vector<T>& v)
 static void free_batch(ks_batch* b)
 {
     if (!b) return;
+    resolve_timers(b);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     else (void)hipDeviceSynchronize();
     for (void* p : b->allocs) (void)hipFree(p);
@@ -206,6 +219,7 @@ void ks_default_options(ks_options* o)
     o->diis_space = 8;
     o->jk_chunks = 0;
     o->xc_chunks = 0;
+    o->guess = KS_GUESS_ATOM;
 }
 
 const char* ks_last_error(void) { return g_err; }
@@ -254,10 +268,18 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         set_error("unknown xc or precision option");
         return KS_EINVAL;
     }
+    if (opt.guess != KS_GUESS_ATOM && opt.guess != KS_GUESS_CORE) {
+        set_error("unknown guess option %d", opt.guess);
+        return KS_EINVAL;
+    }
     if (opt.n_rad < 1 || opt.n_theta < 1 || opt.n_phi < 1 || opt.max_iter < 1 || opt.diis_space < 1 ||
         opt.diis_space > kMaxDiis || !(opt.e_tol > 0) || !(opt.comm_tol > 0)) {
         set_error("grid sizes, max_iter >= 1, 1 <= diis_space <= %d and positive tolerances required", kMaxDiis);
         return KS_EINVAL;
+    }
+    if (opt.prec == KS_MIXED) {
+        opt.e_tol = std::max(opt.e_tol, kMixedETol);
+        opt.comm_tol = std::max(opt.comm_tol, kMixedCommTol);
     }
     b->opt = opt;
     b->stream = (hipStream_t)stream;
@@ -395,7 +417,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     const int jk_chunks = opt.jk_chunks > 0 ? opt.jk_chunks : std::max(1, std::min(64, (512 + n_mol - 1) / n_mol));
     for (int m = 0; m < n_mol; m++)
         for (int c = 0; c < jk_chunks; c++) b->jk_items.push_back(JkItem{m, c, jk_chunks, 0});
-    const int bp = opt.prec == KS_MIXED ? 64 : 32;
+    const int bp = xc_block_points(b);
     std::vector<int> xc_first;
     for (int m = 0; m < n_mol; m++) {
         xc_first.push_back((int)b->xc_items.size());
@@ -449,7 +471,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     std::memset(s0.data(), 0, sizeof(MolState) * n_mol);
     if ((st = upload(b, &b->d_state, s0))) return st;
     double** mats[] = {&b->d_S, &b->d_T, &b->d_V, &b->d_H, &b->d_X, &b->d_F, &b->d_P,
-                       &b->d_J, &b->d_K, &b->d_Vxc, &b->d_Fp, &b->d_C};
+                       &b->d_J, &b->d_K, &b->d_Vxc, &b->d_Fp, &b->d_C, &b->d_Pprev};
     for (double** p : mats)
         if ((st = dev_alloc(b, p, (size_t)b->nmat))) return st;
     if ((st = dev_alloc(b, &b->d_eps, (size_t)ao0))) return st;
@@ -471,6 +493,9 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     if ((st = dev_alloc(b, &b->d_eterms, 6 * (size_t)n_mol))) return st;
     KS_HIP(hipHostMalloc((void**)&b->h_nactive, sizeof(int), hipHostMallocDefault));
     KS_HIP(hipMemsetAsync(b->d_Vxc, 0, sizeof(double) * b->nmat, b->stream));
+    KS_HIP(hipMemsetAsync(b->d_J, 0, sizeof(double) * b->nmat, b->stream));
+    KS_HIP(hipMemsetAsync(b->d_K, 0, sizeof(double) * b->nmat, b->stream));
+    KS_HIP(hipMemsetAsync(b->d_Pprev, 0, sizeof(double) * b->nmat, b->stream));
     KS_HIP(hipMemsetAsync(b->d_exc, 0, sizeof(double) * n_mol, b->stream));
     KS_HIP(hipStreamSynchronize(b->stream));
     return KS_OK;
@@ -570,7 +595,7 @@ ks_status jk_build(ks_batch* b, const void* P, void* J, void* K)
         set_error("jk_build before eri_build");
         return KS_ESTATE;
     }
-    ks_status st = launch_jk(b, (const double*)P, (double*)J, (double*)K, false);
+    ks_status st = launch_jk(b, (const double*)P, (double*)J, (double*)K, false, false, false);
     if (st) return st;
     KS_HIP(hipStreamSynchronize(b->stream));
     return KS_OK;
@@ -604,7 +629,7 @@ ks_status fock_build(ks_batch* b, const void* Pin, void* F, double* E_terms)
     ks_status st;
     if (!b->eri_done && (st = eri_build(b))) return st;
     const double* P = Pin ? (const double*)Pin : b->d_P;
-    if ((st = launch_jk(b, P, b->d_J, b->d_K, false))) return st;
+    if ((st = launch_jk(b, P, b->d_J, b->d_K, false, false, true))) return st;
     if (b->opt.xc != KS_XC_HF) {
         if ((st = launch_xc(b, P, b->d_Vxc, false))) return st;
     }
@@ -621,7 +646,9 @@ ks_status scf_step(ks_batch* b, int* n_active)
     CHECK_B(b);
     ks_status st;
     if (!b->eri_done && (st = eri_build(b))) return st;
-    if ((st = launch_jk(b, b->d_P, b->d_J, b->d_K, true))) return st;
+    // mixed path: incremental J/K from P - Pprev (FP32 digest, FP64 accumulation)
+    const bool inc = b->opt.prec == KS_MIXED;
+    if ((st = launch_jk(b, b->d_P, b->d_J, b->d_K, true, inc, true))) return st;
     if (b->opt.xc != KS_XC_HF && (st = launch_xc(b, b->d_P, b->d_Vxc, true))) return st;
     if ((st = launch_fock(b, b->d_P, b->d_J, b->d_K, b->d_Vxc, b->d_F, true, nullptr))) return st;
     if ((st = launch_iteration_tail(b))) return st;
@@ -738,6 +765,7 @@ ks_status ks_get_grid(const ks_batch* b, int mol, double* out)
 void ks_set_timing(ks_batch* b, int on)
 {
     if (!b) return;
+    resolve_timers(b);
     b->timing = on != 0;
     b->tnames.clear();
     b->tms.clear();
@@ -746,12 +774,39 @@ void ks_set_timing(ks_batch* b, int on)
 int ks_kernel_times(const ks_batch* b, const char** names, double* ms, int cap)
 {
     if (!b) return 0;
+    ks_batch* bb = const_cast<ks_batch*>(b);
+    resolve_timers(bb);
     int n = (int)b->tnames.size();
     for (int i = 0; i < n && i < cap; i++) {
         names[i] = b->tnames[i].c_str();
         ms[i] = b->tms[2 * i] / std::max(1.0, b->tms[2 * i + 1]);
     }
     return n;
+}
+
+int ks_kernel_counts(const ks_batch* b, double* launches, int cap)
+{
+    if (!b) return 0;
+    resolve_timers(const_cast<ks_batch*>(b));
+    int n = (int)b->tnames.size();
+    for (int i = 0; i < n && i < cap; i++) launches[i] = b->tms[2 * i + 1];
+    return n;
+}
+
+ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, double* err)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol) {
+        set_error("molecule index %d out of range", mol);
+        return KS_EINVAL;
+    }
+    MolState s;
+    KS_HIP(hipMemcpyAsync(&s, b->d_state + mol, sizeof(MolState), hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    if (E) *E = s.E;
+    if (dE) *dE = s.E - s.Eprev;
+    if (err) *err = s.err;
+    return KS_OK;
 }
 
 }  // extern "C"

@@ -43,6 +43,7 @@ struct JkArgs {
     const void* eri[kNClass];
     long nq[kNClass];
     const double* P;
+    const double* Pref;     // incremental build: digest P - Pref (NULL: P itself)
     void* part;             // [items][2][np_max^2]
     long part_stride;       // np_max^2
     int only_active;
@@ -160,8 +161,9 @@ __global__ __launch_bounds__(256) void jk_kernel(JkArgs g)
     A* AJ = Ps + NN;
     A* AK = AJ + NN;
     const double* P = g.P + md.mat0;
+    const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-        Ps[i] = A(P[i]);
+        Ps[i] = A(Pr ? P[i] - Pr[i] : P[i]);
         AJ[i] = A(0);
         AK[i] = A(0);
     }
@@ -180,11 +182,14 @@ __global__ __launch_bounds__(256) void jk_kernel(JkArgs g)
     }
 }
 
-// J = sum_chunks (AJ + AJ^T), K = sum_chunks (AK + AK^T), in FP64.
+// J = sum_chunks (AJ + AJ^T), K = sum_chunks (AK + AK^T), in FP64; added to
+// J, K when accumulate is set (incremental build).  Pnext, when given, is
+// copied to Pref: the density the accumulated J, K now correspond to.
 template <typename A>
 __global__ void jk_reduce_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state, int nchunk,
-                                 const A* __restrict__ part, long stride, int only_active, double* __restrict__ J,
-                                 double* __restrict__ K)
+                                 const A* __restrict__ part, long stride, int only_active, int accumulate,
+                                 const double* __restrict__ Pnext, double* __restrict__ Pref,
+                                 double* __restrict__ J, double* __restrict__ K)
 {
     const int m = blockIdx.y;
     if (only_active && state[m].status != KS_MOL_ACTIVE) return;
@@ -200,8 +205,14 @@ __global__ void jk_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
         sj += (double)pj[mu * N + nu] + (double)pj[nu * N + mu];
         sk += (double)pk[mu * N + nu] + (double)pk[nu * N + mu];
     }
-    J[md.mat0 + t] = sj;
-    K[md.mat0 + t] = sk;
+    if (accumulate) {
+        J[md.mat0 + t] += sj;
+        K[md.mat0 + t] += sk;
+    } else {
+        J[md.mat0 + t] = sj;
+        K[md.mat0 + t] = sk;
+    }
+    if (Pnext) Pref[md.mat0 + t] = Pnext[md.mat0 + t];
 }
 
 size_t jk_lds_bytes(const ks_batch* b)
@@ -213,7 +224,8 @@ size_t jk_lds_bytes(const ks_batch* b)
 }
 
 template <typename S, typename A>
-static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active)
+static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
+                        bool track)
 {
     JkArgs g;
     g.mol = b->d_mol;
@@ -226,27 +238,33 @@ static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool
         g.nq[c] = b->nq[c];
     }
     g.P = P;
+    g.Pref = incremental ? b->d_Pprev : nullptr;
     g.part = b->d_jk_part;
     g.part_stride = (long)b->max_np * b->max_np;
     g.only_active = only_active;
     const size_t lds = jk_lds_bytes(b);
     KS_HIP(hipFuncSetAttribute((const void*)jk_kernel<S, A>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((jk_kernel<S, A>), dim3((unsigned)b->jk_items.size()), dim3(256), lds, b->stream, g);
+    {
+        KTimer tm(b, "jk");
+        hipLaunchKernelGGL((jk_kernel<S, A>), dim3((unsigned)b->jk_items.size()), dim3(256), lds, b->stream, g);
+    }
     KS_HIP(hipGetLastError());
+    KTimer tr(b, "jk_reduce");
     const int nchunk = b->jk_items.empty() ? 1 : b->jk_items[0].nchunk;
     int maxnn = 0;
     for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
     hipLaunchKernelGGL(jk_reduce_kernel<A>, dim3((maxnn + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
-                       b->d_state, nchunk, (const A*)b->d_jk_part, g.part_stride, (int)only_active, J, K);
+                       b->d_state, nchunk, (const A*)b->d_jk_part, g.part_stride, (int)only_active, (int)incremental,
+                       track ? P : nullptr, b->d_Pprev, J, K);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
 
-ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active)
+ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
+                    bool track)
 {
-    KTimer tm(b, "jk");
-    if (b->opt.prec == KS_MIXED) return run_jk<float, float>(b, P, J, K, only_active);
-    return run_jk<double, double>(b, P, J, K, only_active);
+    if (b->opt.prec == KS_MIXED) return run_jk<float, float>(b, P, J, K, only_active, incremental, track);
+    return run_jk<double, double>(b, P, J, K, only_active, incremental, track);
 }
 
 }  // namespace ks

@@ -258,6 +258,34 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
     }
 }
 
+// Diagonal atomic-occupation density: H 1s 1; C/N/O/F 1s 2, 2s 2, 2p (Z-4)/3
+// per component, scaled so that tr(P S) = tr(P) = N_e.
+__global__ __launch_bounds__(kScfThreads) void atom_guess_kernel(const MolDesc* __restrict__ mols,
+                                                                 const Shell* __restrict__ shells,
+                                                                 const double* __restrict__ Zat, double* __restrict__ P)
+{
+    __shared__ double red[2 * kScfThreads / 64];
+    const int m = blockIdx.x;
+    const MolDesc md = mols[m];
+    const int N = md.nbf;
+    double* Pm = P + md.mat0;
+    for (int t = threadIdx.x; t < N * N; t += blockDim.x) Pm[t] = 0.0;
+    __syncthreads();
+    double s = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < md.nshell; i += blockDim.x) {
+        const Shell& sh = shells[md.shell0 + i];
+        const double Z = Zat[md.atom0 + sh.atom];
+        const double occ = Z == 1.0 ? 1.0 : (sh.L == 1 ? (Z - 4.0) / 3.0 : 2.0);
+        for (int k = 0; k < (sh.L ? 3 : 1); k++) {
+            Pm[(sh.ao + k) * N + sh.ao + k] = occ;
+            two_sum_add(s, c, occ);
+        }
+    }
+    const double tot = block_sum(s, c, red);
+    const double scale = 2.0 * md.nocc / tot;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) Pm[i * N + i] *= scale;
+}
+
 // W = X^T A X (guess from the core Hamiltonian)
 __global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const double* __restrict__ A)
 {
@@ -493,6 +521,12 @@ ks_status launch_lowdin(ks_batch* b)
 ks_status launch_guess(ks_batch* b)
 {
     KTimer tm(b, "guess");
+    if (b->opt.guess == KS_GUESS_ATOM) {
+        hipLaunchKernelGGL(atom_guess_kernel, dim3(b->n_mol), dim3(kScfThreads), 0, b->stream, b->d_mol, b->d_shells,
+                           b->d_Zc, b->d_P);
+        KS_HIP(hipGetLastError());
+        return KS_OK;
+    }
     ScfArgs g = scf_args(b, false);
     hipLaunchKernelGGL(xtax_kernel, dim3(b->n_mol), dim3(kScfThreads), 0, b->stream, g, (const double*)b->d_H);
     KS_HIP(hipGetLastError());

@@ -211,21 +211,19 @@ struct XcArgs {
 constexpr int kXcThreads = 512;
 constexpr int kXcWaves = kXcThreads / 64;
 
-template <typename T> struct XcBlock;
-template <> struct XcBlock<double> { static constexpr int BP = 32; };
-template <> struct XcBlock<float> { static constexpr int BP = 64; };
-
-template <typename T>
-__host__ __device__ constexpr size_t xc_lds_bytes_for(int np)
+// LDS: points, per-point coefficients, the padded density (the MFMA B
+// operand of X = Phi P, reused by every sub-block), Phi, grad Phi, X / W.
+__host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int np)
 {
-    return (size_t)5 * XcBlock<T>::BP * (np + 1) * sizeof(T) + (size_t)XcBlock<T>::BP * 4 * sizeof(double)
-           + (size_t)XcBlock<T>::BP * 4 * sizeof(T) + kXcWaves * sizeof(double) + 64;
+    return (size_t)bp * 4 * sizeof(double) + kXcWaves * sizeof(double) + (size_t)bp * 4 * es
+           + (size_t)np * np * es + (size_t)5 * bp * (np + 1) * es + 64;
 }
 
-template <typename T, int MAXT>
+constexpr size_t kLdsMax = 163840;
+
+template <typename T, int BP, int MAXT>
 __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
 {
-    constexpr int BP = XcBlock<T>::BP;
     constexpr int TPP = kXcThreads / BP;     // threads per point in the density reduction
     typedef typename Mfma<T>::V V;
     const XcItem it = g.items[blockIdx.x];
@@ -240,13 +238,15 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
     double* pts = (double*)smem_xc;                          // [BP][4]
     double* wsum = pts + BP * 4;                              // [waves]
     T* coef = (T*)(wsum + kXcWaves);                          // [BP][4]
-    T* Phi = coef + BP * 4;                                   // [BP][LD]
+    T* Pl = coef + BP * 4;                                    // [NP][NP]
+    T* Phi = Pl + NP * NP;                                    // [BP][LD]
     T* dPhi = Phi + BP * LD;                                  // [3][BP][LD]
     T* XW = dPhi + 3 * BP * LD;                               // [BP][LD]
 
     const T* __restrict__ Pt = (const T*)g.Pt + g.ptoff[m];
     const Shell* __restrict__ sh = g.shells + md.shell0;
 
+    for (int i = tid; i < NP * NP; i += kXcThreads) Pl[i] = Pt[i];
     for (int i = tid; i < 5 * BP * LD; i += kXcThreads) Phi[i] = T(0);
 
     V acc[MAXT];
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
             for (int r = 0; r < 4; r++) c[r] = T(0);
             for (int kk = 0; kk < NP; kk += 4) {
                 const T a = Phi[(gt * 16 + l16) * LD + kk + l4];
-                const T bb = Pt[(kk + l4) * NP + nt * 16 + l16];
+                const T bb = Pl[(kk + l4) * NP + nt * 16 + l16];
                 c = Mfma<T>::run(a, bb, c);
             }
 #pragma unroll
@@ -442,13 +442,28 @@ __global__ void xc_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
     V[md.mat0 + t] = v;
 }
 
+// Points per sub-block: 32 (FP64) / 64 (FP32) when the LDS budget allows,
+// half that for the largest molecules.
+template <typename T> struct XcBig;
+template <> struct XcBig<double> { static constexpr int BP = 32; };
+template <> struct XcBig<float> { static constexpr int BP = 64; };
+
+int xc_block_points(const ks_batch* b)
+{
+    const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
+    const int big = b->opt.prec == KS_MIXED ? 64 : 32;
+    return xc_lds_bytes_for(es, big, b->max_np) <= kLdsMax ? big : big / 2;
+}
+
 template <typename T>
 static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_active)
 {
     int maxnp2 = 0;
     for (auto& m : b->mol) maxnp2 = std::max(maxnp2, m.np * m.np);
+    KTimer* tp = new KTimer(b, "xc_pad");
     hipLaunchKernelGGL(pad_density_kernel<T>, dim3((maxnp2 + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
                        b->d_state, b->d_ptoff, P, (T*)b->d_Pt, (int)only_active);
+    delete tp;
     KS_HIP(hipGetLastError());
     XcArgs g;
     g.mol = b->d_mol;
@@ -463,19 +478,25 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
     g.part_stride = (long)b->max_np * b->max_np;
     g.vwn5 = b->opt.xc == KS_XC_B3LYP5;
     g.only_active = only_active;
-    const size_t lds = xc_lds_bytes_for<T>(b->max_np);
-    const int nt = b->max_np / 16, maxt = (nt * nt + kXcWaves - 1) / kXcWaves;
+    const int bp = xc_block_points(b);
+    const size_t lds = xc_lds_bytes_for(sizeof(T), bp, b->max_np);
     const dim3 grid((unsigned)b->xc_items.size());
-    if (maxt <= 4) {
-        KS_HIP(hipFuncSetAttribute((const void*)xc_kernel<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((xc_kernel<T, 4>), grid, dim3(kXcThreads), lds, b->stream, g);
-    } else {
-        KS_HIP(hipFuncSetAttribute((const void*)xc_kernel<T, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((xc_kernel<T, 5>), grid, dim3(kXcThreads), lds, b->stream, g);
-    }
+    const void* fn = b->max_np <= 80 ? (bp == XcBig<T>::BP ? (const void*)xc_kernel<T, XcBig<T>::BP, 4>
+                                                          : (const void*)xc_kernel<T, XcBig<T>::BP / 2, 4>)
+                                     : (const void*)xc_kernel<T, XcBig<T>::BP / 2, 5>;
+    KS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    KTimer* tx = new KTimer(b, "xc");
+    if (b->max_np <= 80 && bp == XcBig<T>::BP)
+        hipLaunchKernelGGL((xc_kernel<T, XcBig<T>::BP, 4>), grid, dim3(kXcThreads), lds, b->stream, g);
+    else if (b->max_np <= 80)
+        hipLaunchKernelGGL((xc_kernel<T, XcBig<T>::BP / 2, 4>), grid, dim3(kXcThreads), lds, b->stream, g);
+    else
+        hipLaunchKernelGGL((xc_kernel<T, XcBig<T>::BP / 2, 5>), grid, dim3(kXcThreads), lds, b->stream, g);
+    delete tx;
     KS_HIP(hipGetLastError());
     int maxnn = 0;
     for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
+    KTimer tr(b, "xc_reduce");
     hipLaunchKernelGGL(xc_reduce_kernel<T>, dim3((maxnn + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
                        b->d_state, b->d_xc_first, (const T*)b->d_xc_part, g.part_stride, b->d_xc_exc,
                        (int)only_active, V, b->d_exc);
@@ -485,14 +506,14 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
 
 ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active)
 {
-    KTimer tm(b, "xc");
     if (b->opt.prec == KS_MIXED) return run_xc<float>(b, P, V, only_active);
     return run_xc<double>(b, P, V, only_active);
 }
 
 size_t xc_lds_bytes(const ks_batch* b)
 {
-    return b->opt.prec == KS_MIXED ? xc_lds_bytes_for<float>(b->max_np) : xc_lds_bytes_for<double>(b->max_np);
+    const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
+    return xc_lds_bytes_for(es, xc_block_points(b), b->max_np);
 }
 
 }  // namespace ks

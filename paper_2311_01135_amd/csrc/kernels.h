@@ -25,6 +25,7 @@ struct KTimer {
     KTimer(ks_batch* b_, const char* n);
     ~KTimer();
 };
+void resolve_timers(ks_batch* b);
 
 // integrals (k_ints.hip)
 void build_boys_table(std::vector<double>& tab);
@@ -34,13 +35,16 @@ ks_status launch_eri(ks_batch* b);
 ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out);
 
 // J/K (k_jk.hip)
-ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active);
+// incremental: digest P - Pprev and add to J, K; track: afterwards Pprev = P.
+ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
+                    bool track);
 size_t jk_lds_bytes(const ks_batch* b);
 
 // grid and XC (k_xc.hip)
 ks_status launch_grid(ks_batch* b);
 ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active);
 size_t xc_lds_bytes(const ks_batch* b);
+int xc_block_points(const ks_batch* b);
 
 // SCF steps (k_scf.hip)
 ks_status launch_fock(ks_batch* b, const double* P, const double* J, const double* K, const double* Vxc,

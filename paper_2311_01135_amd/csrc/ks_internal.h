@@ -19,6 +19,10 @@ constexpr int kMaxDiis = 8;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kBohrAng = 0.52917721092;
 constexpr double kRhoCut = 1e-12;      // points below this density carry no XC
+// Convergence thresholds are raised to these in the mixed path: the FP32
+// Fock matrix carries ~1e-6 noise, below which FP32 cannot resolve changes.
+constexpr double kMixedETol = 1e-6;
+constexpr double kMixedCommTol = 1e-5;
 
 // Boys-function table: F_m(T_i), T_i = i * kBoysDT, i < kBoysNT, m < kBoysM.
 constexpr double kBoysDT = 0.05;
@@ -142,6 +146,7 @@ struct ks_batch {
     double *d_F = nullptr, *d_P = nullptr, *d_J = nullptr, *d_K = nullptr, *d_Vxc = nullptr;
     double *d_Fp = nullptr, *d_C = nullptr, *d_eps = nullptr, *d_work = nullptr;
     double *d_Fh = nullptr, *d_Eh = nullptr;    // DIIS history (diis_space * nmat each)
+    double* d_Pprev = nullptr;      // density the resident J, K were built from (mixed path)
     void* d_Pt = nullptr;           // padded density in the XC compute type (np^2 per molecule)
     long* d_ptoff = nullptr;        // offsets of d_Pt blocks
     long npt_total = 0;
@@ -165,5 +170,7 @@ struct ks_batch {
 
     bool timing = false;
     std::vector<std::string> tnames;
-    std::vector<double> tms;
+    std::vector<double> tms;        // per name: total ms, launches
+    struct Pending { int name; hipEvent_t e0, e1; };
+    std::vector<Pending> pending;   // events not yet read back
 };

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libks.so")
 
 KS_XC_HF, KS_XC_B3LYP, KS_XC_B3LYP5 = 0, 1, 2
 KS_FP64, KS_MIXED = 0, 1
+KS_GUESS_ATOM, KS_GUESS_CORE = 0, 1
 MOL_ACTIVE, MOL_CONVERGED, MOL_MAXITER, MOL_DIVERGED = 0, 1, 2, 3
 MATRIX = {"S": 0, "T": 1, "V": 2, "X": 3, "F": 4, "P": 5, "J": 6, "K": 7, "Vxc": 8}
 STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", -4: "KS_ENOCONV",
@@ -26,7 +27,8 @@ STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", 
 
 EXPORTS = ["ks_default_options", "ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup",
            "eri_build", "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "ks_get_result",
-           "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_kernel_times", "ks_set_timing",
+           "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence", "ks_kernel_times",
+           "ks_kernel_counts", "ks_set_timing",
            "ks_batch_destroy", "ks_last_error"]
 
 
@@ -40,7 +42,7 @@ class Options(C.Structure):
     _fields_ = [("xc", C.c_int), ("prec", C.c_int), ("n_rad", C.c_int), ("n_theta", C.c_int),
                 ("n_phi", C.c_int), ("e_tol", C.c_double), ("comm_tol", C.c_double),
                 ("max_iter", C.c_int), ("diis_space", C.c_int), ("jk_chunks", C.c_int),
-                ("xc_chunks", C.c_int)]
+                ("xc_chunks", C.c_int), ("guess", C.c_int)]
 
 
 _lib = None
@@ -72,6 +74,10 @@ def load():
     L.ks_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), dp, C.c_int]
     L.ks_kernel_times.restype = C.c_int
     L.ks_set_timing.argtypes = [vp, C.c_int]
+    L.ks_kernel_counts.argtypes = [vp, dp, C.c_int]
+    L.ks_kernel_counts.restype = C.c_int
+    L.ks_get_convergence.argtypes = [vp, C.c_int, dp, dp, dp]
+    L.ks_get_convergence.restype = C.c_int
     L.ks_batch_destroy.argtypes = [vp]
     L.ks_batch_destroy.restype = None
     L.ks_last_error.restype = C.c_char_p
@@ -132,9 +138,10 @@ class Batch:
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
-        if getattr(self, "h", None):
-            load().ks_batch_destroy(self.h)
-            self.h = None
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.ks_batch_destroy(h)
+        self.h = None
 
     def __del__(self):
         self.close()
@@ -186,7 +193,14 @@ class Batch:
         names = (C.c_char_p * 64)()
         ms = (C.c_double * 64)()
         n = load().ks_kernel_times(self.h, names, ms, 64)
-        return {names[i].decode(): ms[i] for i in range(min(n, 64))}
+        cnt = (C.c_double * 64)()
+        load().ks_kernel_counts(self.h, cnt, 64)
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(n, 64))}
+
+    def convergence(self, m):
+        E, dE, err = C.c_double(), C.c_double(), C.c_double()
+        _check(load().ks_get_convergence(self.h, m, C.byref(E), C.byref(dE), C.byref(err)))
+        return E.value, dE.value, err.value
 
     # -- results ----------------------------------------------------------
     def result(self, m):
