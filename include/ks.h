@@ -78,6 +78,8 @@ typedef struct {
     int jk_chunks;          /* work groups per molecule for J/K (0 = automatic) */
     int xc_chunks;          /* work groups per molecule for XC (0 = automatic) */
     int guess;              /* initial density: KS_GUESS_ATOM or KS_GUESS_CORE */
+    int xc_points;          /* XC launch shape: grid points per sub-block, 16/32/64 (0 = tuned default) */
+    int xc_waves;           /* XC launch shape: wavefronts per work group, 4 or 8 (0 = tuned default) */
 } ks_options;
 
 /* Initial density.  The paper only says C_1 is initialised (section 3.1).

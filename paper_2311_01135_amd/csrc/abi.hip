@@ -220,6 +220,8 @@ void ks_default_options(ks_options* o)
     o->jk_chunks = 0;
     o->xc_chunks = 0;
     o->guess = KS_GUESS_ATOM;
+    o->xc_points = 0;
+    o->xc_waves = 0;
 }
 
 const char* ks_last_error(void) { return g_err; }
@@ -414,7 +416,8 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     for (int c = 0; c < kNClass; c++) b->nq[c] = qoff[c];
 
     // work items
-    const int jk_chunks = opt.jk_chunks > 0 ? opt.jk_chunks : std::max(1, std::min(64, (512 + n_mol - 1) / n_mol));
+    // default: ~2048 J/K work groups per launch (8 per molecule at 256 molecules)
+    const int jk_chunks = opt.jk_chunks > 0 ? opt.jk_chunks : std::max(1, std::min(64, (2048 + n_mol - 1) / n_mol));
     for (int m = 0; m < n_mol; m++)
         for (int c = 0; c < jk_chunks; c++) b->jk_items.push_back(JkItem{m, c, jk_chunks, 0});
     const int bp = xc_block_points(b);
@@ -422,7 +425,9 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     for (int m = 0; m < n_mol; m++) {
         xc_first.push_back((int)b->xc_items.size());
         const MolDesc& md = b->mol[m];
-        long nch = opt.xc_chunks > 0 ? opt.xc_chunks : std::max(1, (2048 + n_mol - 1) / n_mol);
+        // default: ~4096 work groups per launch (16 per molecule at 256
+        // molecules), at most 64 per molecule
+        long nch = opt.xc_chunks > 0 ? opt.xc_chunks : std::max(1, std::min(64, (4096 + n_mol - 1) / n_mol));
         nch = std::max(1L, std::min(nch, md.ngrid / (4L * bp)));
         for (long c = 0; c < nch; c++) {
             XcItem it{};
@@ -483,7 +488,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     unsigned char* tmp;
     if ((st = dev_alloc(b, &tmp, es * (size_t)pt))) return st;
     b->d_Pt = tmp;
-    if ((st = dev_alloc(b, &tmp, es * 2 * np2 * b->jk_items.size()))) return st;
+    if ((st = dev_alloc(b, &tmp, sizeof(double) * 2 * np2 * b->jk_items.size()))) return st;
     b->d_jk_part = tmp;
     if ((st = dev_alloc(b, &tmp, es * np2 * b->xc_items.size()))) return st;
     b->d_xc_part = tmp;

@@ -215,9 +215,21 @@ __global__ void jk_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
     if (Pnext) Pref[md.mat0 + t] = Pnext[md.mat0 + t];
 }
 
+// LDS accumulation type: FP64 whenever 3 N^2 doubles fit the 160 KB LDS.
+// The digest is bound by its LDS atomics, and on gfx950 ds_add_f64 runs at
+// twice the rate of ds_add_f32 here, so the mixed path stores its ERIs in
+// FP32 (half the HBM stream) but accumulates J/K in FP64; molecules above 82
+// functions fall back to FP32 accumulation.
+bool jk_acc_fp64(const ks_batch* b)
+{
+    int maxn = 0;
+    for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
+    return 3 * (size_t)maxn * maxn * sizeof(double) <= 163840;
+}
+
 size_t jk_lds_bytes(const ks_batch* b)
 {
-    const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
+    const size_t es = jk_acc_fp64(b) ? sizeof(double) : sizeof(float);
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
     return 3 * (size_t)maxn * maxn * es;
@@ -263,6 +275,7 @@ static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool
 ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
                     bool track)
 {
+    if (b->opt.prec == KS_MIXED && jk_acc_fp64(b)) return run_jk<float, double>(b, P, J, K, only_active, incremental, track);
     if (b->opt.prec == KS_MIXED) return run_jk<float, float>(b, P, J, K, only_active, incremental, track);
     return run_jk<double, double>(b, P, J, K, only_active, incremental, track);
 }

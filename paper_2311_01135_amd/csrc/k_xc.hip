@@ -178,6 +178,11 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
 
+// exp in the compute type: FP64 libm exp; FP32 hardware exp2 (v_exp_f32) of
+// x log2(e), relative error ~|x| 1e-7 for the |x| < 40 used by the AO values.
+__device__ __forceinline__ double fast_exp(double x) { return exp(x); }
+__device__ __forceinline__ float fast_exp(float x) { return __expf(x); }
+
 // padded copy of P in the compute type: Pt[m] is np x np, zero outside nbf.
 template <typename T>
 __global__ void pad_density_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state,
@@ -208,23 +213,85 @@ struct XcArgs {
     int only_active;
 };
 
-constexpr int kXcThreads = 512;
-constexpr int kXcWaves = kXcThreads / 64;
-
+// Launch shapes.  BP points per sub-block, NW wavefronts per work group.
 // LDS: points, per-point coefficients, the padded density (the MFMA B
 // operand of X = Phi P, reused by every sub-block), Phi, grad Phi, X / W.
-__host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int np)
+__host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np)
 {
-    return (size_t)bp * 4 * sizeof(double) + kXcWaves * sizeof(double) + (size_t)bp * 4 * es
+    return (size_t)bp * 4 * sizeof(double) + (size_t)nw * sizeof(double) + (size_t)bp * 4 * es
            + (size_t)np * np * es + (size_t)5 * bp * (np + 1) * es + 64;
 }
 
 constexpr size_t kLdsMax = 163840;
 
-template <typename T, int BP, int MAXT>
-__global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
+// X tiles (t = wave + NW j, j < NJ) of X = Phi P: NJ independent MFMA chains,
+// K = NP (a multiple of 16) unrolled by 16; no branches inside the loop.
+template <typename T, int NW, int NJ>
+__device__ __forceinline__ void gemm_phi_p(const T* __restrict__ Phi, const T* __restrict__ Pl, T* __restrict__ XW,
+                                           int LD, int NP, int NT, int wave, int lane)
 {
-    constexpr int TPP = kXcThreads / BP;     // threads per point in the density reduction
+    typedef typename Mfma<T>::V V;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    V c[NJ];
+    int ra[NJ], cb[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int t = wave + j * NW;
+        ra[j] = (t / NT) * 16 + l16;
+        cb[j] = (t % NT) * 16 + l16;
+#pragma unroll
+        for (int r = 0; r < 4; r++) c[j][r] = T(0);
+    }
+    for (int kk = 0; kk < NP; kk += 16) {
+#pragma unroll
+        for (int k4 = 0; k4 < 16; k4 += 4) {
+#pragma unroll
+            for (int j = 0; j < NJ; j++) {
+                const T a = Phi[ra[j] * LD + kk + k4 + l4];
+                const T b = Pl[(kk + k4 + l4) * NP + cb[j]];
+                c[j] = Mfma<T>::run(a, b, c[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r0 = ((wave + j * NW) / NT) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; r++) XW[(r0 + Mfma<T>::row(lane, r)) * LD + cb[j]] = c[j][r];
+    }
+}
+
+// acc[j] += tile (t = wave + NW j) of Phi^T W over the BP points of a sub-block.
+template <typename T, int NW, int BP, int MAXT, int NJ>
+__device__ __forceinline__ void gemm_phit_w(const T* __restrict__ Phi, const T* __restrict__ XW, int LD, int NT,
+                                            int wave, int lane, typename Mfma<T>::V (&acc)[MAXT])
+{
+    if constexpr (NJ <= MAXT) {
+        const int l16 = lane & 15, l4 = lane >> 4;
+        int ca[NJ], cb[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            const int t = wave + j * NW;
+            ca[j] = (t / NT) * 16 + l16;
+            cb[j] = (t % NT) * 16 + l16;
+        }
+#pragma unroll 2
+        for (int kk = 0; kk < BP; kk += 4) {
+#pragma unroll
+            for (int j = 0; j < NJ; j++) {
+                const T a = Phi[(kk + l4) * LD + ca[j]];
+                const T b = XW[(kk + l4) * LD + cb[j]];
+                acc[j] = Mfma<T>::run(a, b, acc[j]);
+            }
+        }
+    }
+}
+
+template <typename T, int BP, int NW, int MAXT>
+__global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
+{
+    constexpr int NTH = NW * 64;
+    constexpr int TPP = NTH / BP;     // threads per point in the density reduction
     typedef typename Mfma<T>::V V;
     const XcItem it = g.items[blockIdx.x];
     const int m = it.mol;
@@ -232,12 +299,14 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
     const MolDesc md = g.mol[m];
     const int N = md.nbf, NP = md.np, NT = NP >> 4, LD = NP + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l16 = lane & 15, l4 = lane >> 4;
+    const int l16 = lane & 15;
+    const int nj1 = ((BP / 16) * NT - wave + NW - 1) / NW;   // Phi P tiles of this wave
+    const int nj2 = (NT * NT - wave + NW - 1) / NW;          // Phi^T W tiles of this wave
 
     extern __shared__ __align__(16) unsigned char smem_xc[];
     double* pts = (double*)smem_xc;                          // [BP][4]
-    double* wsum = pts + BP * 4;                              // [waves]
-    T* coef = (T*)(wsum + kXcWaves);                          // [BP][4]
+    double* wsum = pts + BP * 4;                              // [NW]
+    T* coef = (T*)(wsum + NW);                                // [BP][4]
     T* Pl = coef + BP * 4;                                    // [NP][NP]
     T* Phi = Pl + NP * NP;                                    // [BP][LD]
     T* dPhi = Phi + BP * LD;                                  // [3][BP][LD]
@@ -246,8 +315,8 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
     const T* __restrict__ Pt = (const T*)g.Pt + g.ptoff[m];
     const Shell* __restrict__ sh = g.shells + md.shell0;
 
-    for (int i = tid; i < NP * NP; i += kXcThreads) Pl[i] = Pt[i];
-    for (int i = tid; i < 5 * BP * LD; i += kXcThreads) Phi[i] = T(0);
+    for (int i = tid; i < NP * NP; i += NTH) Pl[i] = Pt[i];
+    for (int i = tid; i < 5 * BP * LD; i += NTH) Phi[i] = T(0);
 
     V acc[MAXT];
 #pragma unroll
@@ -255,29 +324,34 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
 #pragma unroll
         for (int r = 0; r < 4; r++) acc[k][r] = T(0);
 
-    double exc = 0.0, exc_c = 0.0;   // Neumaier pair, one per point-owner thread
+    double exc = 0.0, exc_c = 0.0;   // Neumaier pair of the functional lanes
+    // points beyond the chunk sit far away with zero weight (all AO values vanish)
     const double far[3] = {sh[0].A[0] + 300.0, sh[0].A[1] + 300.0, sh[0].A[2] + 300.0};
+    double nxt[4] = {far[0], far[1], far[2], 0.0};            // prefetched next point
+    if (tid < BP && it.g0 + tid < it.g1) {
+        const double* src = g.grid + 4 * (md.grid0 + it.g0 + tid);
+        nxt[0] = src[0]; nxt[1] = src[1]; nxt[2] = src[2]; nxt[3] = src[3];
+    }
 
     for (long g0 = it.g0; g0 < it.g1; g0 += BP) {
         __syncthreads();
         if (tid < BP) {
-            const long gp = g0 + tid;
+            pts[4 * tid] = nxt[0];
+            pts[4 * tid + 1] = nxt[1];
+            pts[4 * tid + 2] = nxt[2];
+            pts[4 * tid + 3] = nxt[3];
+            // issue the next sub-block's loads; they complete behind this one
+            const long gp = g0 + BP + tid;
             if (gp < it.g1) {
                 const double* src = g.grid + 4 * (md.grid0 + gp);
-                pts[4 * tid] = src[0];
-                pts[4 * tid + 1] = src[1];
-                pts[4 * tid + 2] = src[2];
-                pts[4 * tid + 3] = src[3];
+                nxt[0] = src[0]; nxt[1] = src[1]; nxt[2] = src[2]; nxt[3] = src[3];
             } else {
-                pts[4 * tid] = far[0];
-                pts[4 * tid + 1] = far[1];
-                pts[4 * tid + 2] = far[2];
-                pts[4 * tid + 3] = 0.0;
+                nxt[0] = far[0]; nxt[1] = far[1]; nxt[2] = far[2]; nxt[3] = 0.0;
             }
         }
         __syncthreads();
         // AO values and gradients: item = (point, shell), point fastest
-        for (int itx = tid; itx < BP * md.nshell; itx += kXcThreads) {
+        for (int itx = tid; itx < BP * md.nshell; itx += NTH) {
             const int gi = itx % BP, s = itx / BP;
             const Shell S = sh[s];
             const T dx = (T)(pts[4 * gi] - S.A[0]), dy = (T)(pts[4 * gi + 1] - S.A[1]), dz = (T)(pts[4 * gi + 2] - S.A[2]);
@@ -286,8 +360,8 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
 #pragma unroll
             for (int k = 0; k < kNPrim; k++) {
                 const T ar = (T)S.a[k] * r2;
-                if (ar < T(80)) {
-                    const T e = (T)S.c[k] * exp(-ar);
+                if (ar < T(sizeof(T) == 4 ? 40 : 80)) {
+                    const T e = (T)S.c[k] * fast_exp(-ar);
                     R += e;
                     dR -= T(2) * (T)S.a[k] * e;
                 }
@@ -310,22 +384,19 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
             }
         }
         __syncthreads();
-        // X = Phi P   (BP x NP) . (NP x NP)
-        for (int t = wave; t < (BP / 16) * NT; t += kXcWaves) {
-            const int gt = t / NT, nt = t % NT;
-            V c;
-#pragma unroll
-            for (int r = 0; r < 4; r++) c[r] = T(0);
-            for (int kk = 0; kk < NP; kk += 4) {
-                const T a = Phi[(gt * 16 + l16) * LD + kk + l4];
-                const T bb = Pl[(kk + l4) * NP + nt * 16 + l16];
-                c = Mfma<T>::run(a, bb, c);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; r++) XW[(gt * 16 + Mfma<T>::row(lane, r)) * LD + nt * 16 + l16] = c[r];
+        // X = Phi P   (BP x NP) . (NP x NP): this wave's tiles, dispatched once
+        // to a branch-free body with a compile-time tile count
+        switch (nj1) {
+        case 1: gemm_phi_p<T, NW, 1>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
+        case 2: gemm_phi_p<T, NW, 2>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
+        case 3: gemm_phi_p<T, NW, 3>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
+        case 4: gemm_phi_p<T, NW, 4>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
+        case 5: gemm_phi_p<T, NW, 5>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
+        case 6: gemm_phi_p<T, NW, 6>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
+        default: break;
         }
         __syncthreads();
-        // rho, grad rho per point; functional
+        // rho and grad rho per point (TPP lanes per point), staged in coef
         {
             const int gi = tid / TPP, sub = tid % TPP;
             T r = T(0), gx = T(0), gy = T(0), gz = T(0);
@@ -344,53 +415,60 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
                 gz += __shfl_xor(gz, o, TPP);
             }
             if (sub == 0) {
-                const T w = (T)pts[4 * gi + 3];
-                gx *= T(2); gy *= T(2); gz *= T(2);
-                T c0 = T(0), c1 = T(0), c2 = T(0), c3 = T(0);
-                if (r >= T(kRhoCut) && w != T(0)) {
-                    T e, vr, vs;
-                    b3lyp<T>(r, gx * gx + gy * gy + gz * gz, g.vwn5, e, vr, vs);
-                    const double we = (double)w * (double)e;
-                    const double tt = exc + we;
-                    if (fabs(exc) >= fabs(we)) exc_c += (exc - tt) + we; else exc_c += (we - tt) + exc;
-                    exc = tt;
-                    c0 = T(0.5) * w * vr;
-                    const T s2 = T(2) * w * vs;
-                    c1 = s2 * gx; c2 = s2 * gy; c3 = s2 * gz;
-                }
-                coef[4 * gi] = c0; coef[4 * gi + 1] = c1; coef[4 * gi + 2] = c2; coef[4 * gi + 3] = c3;
+                coef[4 * gi] = r;
+                coef[4 * gi + 1] = T(2) * gx;
+                coef[4 * gi + 2] = T(2) * gy;
+                coef[4 * gi + 3] = T(2) * gz;
             }
         }
         __syncthreads();
+        // functional: one wave, one point per lane (every other wave would
+        // repeat the same instruction stream with most lanes idle)
+        if (wave == 0 && lane < BP) {
+            const int gi = lane;
+            const T r = coef[4 * gi], gx = coef[4 * gi + 1], gy = coef[4 * gi + 2], gz = coef[4 * gi + 3];
+            const T w = (T)pts[4 * gi + 3];
+            T c0 = T(0), c1 = T(0), c2 = T(0), c3 = T(0);
+            if (r >= T(kRhoCut) && w != T(0)) {
+                T e, vr, vs;
+                b3lyp<T>(r, gx * gx + gy * gy + gz * gz, g.vwn5, e, vr, vs);
+                const double we = (double)w * (double)e;
+                const double tt = exc + we;
+                if (fabs(exc) >= fabs(we)) exc_c += (exc - tt) + we; else exc_c += (we - tt) + exc;
+                exc = tt;
+                c0 = T(0.5) * w * vr;
+                const T s2 = T(2) * w * vs;
+                c1 = s2 * gx; c2 = s2 * gy; c3 = s2 * gz;
+            }
+            coef[4 * gi] = c0; coef[4 * gi + 1] = c1; coef[4 * gi + 2] = c2; coef[4 * gi + 3] = c3;
+        }
+        __syncthreads();
         // W = c0 Phi + c . grad Phi   (overwrites X)
-        for (int idx = tid; idx < BP * NP; idx += kXcThreads) {
+        for (int idx = tid; idx < BP * NP; idx += NTH) {
             const int gi = idx / NP, mu = idx % NP;
             XW[gi * LD + mu] = coef[4 * gi] * Phi[gi * LD + mu] + coef[4 * gi + 1] * dPhi[gi * LD + mu]
                              + coef[4 * gi + 2] * dPhi[(BP + gi) * LD + mu] + coef[4 * gi + 3] * dPhi[(2 * BP + gi) * LD + mu];
         }
         __syncthreads();
-        // A += Phi^T W   (NP x BP) . (BP x NP), tiles owned round-robin by wave
-#pragma unroll
-        for (int k = 0; k < MAXT; k++) {
-            const int t = wave + k * kXcWaves;
-            if (t < NT * NT) {
-                const int it2 = t / NT, jt = t % NT;
-                V c = acc[k];
-#pragma unroll 4
-                for (int kk = 0; kk < BP; kk += 4) {
-                    const T a = Phi[(kk + l4) * LD + it2 * 16 + l16];
-                    const T bb = XW[(kk + l4) * LD + jt * 16 + l16];
-                    c = Mfma<T>::run(a, bb, c);
-                }
-                acc[k] = c;
-            }
+        // A += Phi^T W   (NP x BP) . (BP x NP), this wave's tiles
+        switch (nj2) {
+        case 1: gemm_phit_w<T, NW, BP, MAXT, 1>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 2: gemm_phit_w<T, NW, BP, MAXT, 2>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 3: gemm_phit_w<T, NW, BP, MAXT, 3>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 4: gemm_phit_w<T, NW, BP, MAXT, 4>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 5: gemm_phit_w<T, NW, BP, MAXT, 5>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 6: gemm_phit_w<T, NW, BP, MAXT, 6>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 7: gemm_phit_w<T, NW, BP, MAXT, 7>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 8: gemm_phit_w<T, NW, BP, MAXT, 8>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 9: gemm_phit_w<T, NW, BP, MAXT, 9>(Phi, XW, LD, NT, wave, lane, acc); break;
+        default: break;
         }
     }
     // write this chunk's A and E_xc
     T* out = (T*)g.part + (size_t)blockIdx.x * g.part_stride;
 #pragma unroll
     for (int k = 0; k < MAXT; k++) {
-        const int t = wave + k * kXcWaves;
+        const int t = wave + k * NW;
         if (t < NT * NT) {
             const int it2 = t / NT, jt = t % NT;
 #pragma unroll
@@ -405,7 +483,7 @@ __global__ __launch_bounds__(kXcThreads) void xc_kernel(XcArgs g)
     __syncthreads();
     if (tid == 0) {
         double s = 0.0;
-        for (int w = 0; w < kXcWaves; w++) s += wsum[w];
+        for (int w = 0; w < NW; w++) s += wsum[w];
         g.part_exc[blockIdx.x] = s;
     }
 }
@@ -442,17 +520,44 @@ __global__ void xc_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
     V[md.mat0 + t] = v;
 }
 
-// Points per sub-block: 32 (FP64) / 64 (FP32) when the LDS budget allows,
-// half that for the largest molecules.
-template <typename T> struct XcBig;
-template <> struct XcBig<double> { static constexpr int BP = 32; };
-template <> struct XcBig<float> { static constexpr int BP = 64; };
-
-int xc_block_points(const ks_batch* b)
+// Launch shape of the batch: the options' xc_points / xc_waves when given
+// (and the LDS budget allows), else the measured default: 64-point
+// sub-blocks for FP32 and 32 for FP64 with 8-wave groups, halved until the
+// LDS budget (160 KB) holds.
+static bool xc_shape_ok(int bp, int nw)
 {
-    const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
-    const int big = b->opt.prec == KS_MIXED ? 64 : 32;
-    return xc_lds_bytes_for(es, big, b->max_np) <= kLdsMax ? big : big / 2;
+    return (bp == 16 || bp == 32 || bp == 64) && (nw == 4 || nw == 8);
+}
+
+XcShape xc_shape(const ks_batch* b)
+{
+    XcShape s;
+    const bool f32 = b->opt.prec == KS_MIXED;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    s.bp = f32 ? 64 : 32;
+    s.nw = 8;
+    if (b->opt.xc_points > 0 || b->opt.xc_waves > 0) {
+        const int bp = b->opt.xc_points > 0 ? b->opt.xc_points : s.bp;
+        const int nw = b->opt.xc_waves > 0 ? b->opt.xc_waves : s.nw;
+        if (xc_shape_ok(bp, nw)) { s.bp = bp; s.nw = nw; }
+    }
+    while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np) > kLdsMax) s.bp /= 2;
+    s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np);
+    return s;
+}
+
+int xc_block_points(const ks_batch* b) { return xc_shape(b).bp; }
+
+template <typename T, int BP, int NW, int MAXT>
+static ks_status launch_xc_shape(ks_batch* b, const XcArgs& g, size_t lds)
+{
+    KS_HIP(hipFuncSetAttribute((const void*)xc_kernel<T, BP, NW, MAXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    KTimer tx(b, "xc");
+    hipLaunchKernelGGL((xc_kernel<T, BP, NW, MAXT>), dim3((unsigned)b->xc_items.size()), dim3(NW * 64), lds,
+                       b->stream, g);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
 }
 
 template <typename T>
@@ -460,10 +565,11 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
 {
     int maxnp2 = 0;
     for (auto& m : b->mol) maxnp2 = std::max(maxnp2, m.np * m.np);
-    KTimer* tp = new KTimer(b, "xc_pad");
-    hipLaunchKernelGGL(pad_density_kernel<T>, dim3((maxnp2 + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
-                       b->d_state, b->d_ptoff, P, (T*)b->d_Pt, (int)only_active);
-    delete tp;
+    {
+        KTimer tp(b, "xc_pad");
+        hipLaunchKernelGGL(pad_density_kernel<T>, dim3((maxnp2 + 255) / 256, b->n_mol), dim3(256), 0, b->stream,
+                           b->d_mol, b->d_state, b->d_ptoff, P, (T*)b->d_Pt, (int)only_active);
+    }
     KS_HIP(hipGetLastError());
     XcArgs g;
     g.mol = b->d_mol;
@@ -478,22 +584,19 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
     g.part_stride = (long)b->max_np * b->max_np;
     g.vwn5 = b->opt.xc == KS_XC_B3LYP5;
     g.only_active = only_active;
-    const int bp = xc_block_points(b);
-    const size_t lds = xc_lds_bytes_for(sizeof(T), bp, b->max_np);
-    const dim3 grid((unsigned)b->xc_items.size());
-    const void* fn = b->max_np <= 80 ? (bp == XcBig<T>::BP ? (const void*)xc_kernel<T, XcBig<T>::BP, 4>
-                                                          : (const void*)xc_kernel<T, XcBig<T>::BP / 2, 4>)
-                                     : (const void*)xc_kernel<T, XcBig<T>::BP / 2, 5>;
-    KS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    KTimer* tx = new KTimer(b, "xc");
-    if (b->max_np <= 80 && bp == XcBig<T>::BP)
-        hipLaunchKernelGGL((xc_kernel<T, XcBig<T>::BP, 4>), grid, dim3(kXcThreads), lds, b->stream, g);
-    else if (b->max_np <= 80)
-        hipLaunchKernelGGL((xc_kernel<T, XcBig<T>::BP / 2, 4>), grid, dim3(kXcThreads), lds, b->stream, g);
-    else
-        hipLaunchKernelGGL((xc_kernel<T, XcBig<T>::BP / 2, 5>), grid, dim3(kXcThreads), lds, b->stream, g);
-    delete tx;
-    KS_HIP(hipGetLastError());
+    const XcShape s = xc_shape(b);
+    const bool big = b->max_np > 80;     // 6 x 6 tiles of 16
+    ks_status st;
+    if (s.nw == 8) {
+        if (s.bp == 64) st = big ? launch_xc_shape<T, 64, 8, 5>(b, g, s.lds) : launch_xc_shape<T, 64, 8, 4>(b, g, s.lds);
+        else if (s.bp == 32) st = big ? launch_xc_shape<T, 32, 8, 5>(b, g, s.lds) : launch_xc_shape<T, 32, 8, 4>(b, g, s.lds);
+        else st = big ? launch_xc_shape<T, 16, 8, 5>(b, g, s.lds) : launch_xc_shape<T, 16, 8, 4>(b, g, s.lds);
+    } else {
+        if (s.bp == 64) st = big ? launch_xc_shape<T, 64, 4, 9>(b, g, s.lds) : launch_xc_shape<T, 64, 4, 7>(b, g, s.lds);
+        else if (s.bp == 32) st = big ? launch_xc_shape<T, 32, 4, 9>(b, g, s.lds) : launch_xc_shape<T, 32, 4, 7>(b, g, s.lds);
+        else st = big ? launch_xc_shape<T, 16, 4, 9>(b, g, s.lds) : launch_xc_shape<T, 16, 4, 7>(b, g, s.lds);
+    }
+    if (st) return st;
     int maxnn = 0;
     for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
     KTimer tr(b, "xc_reduce");
@@ -510,10 +613,6 @@ ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active)
     return run_xc<double>(b, P, V, only_active);
 }
 
-size_t xc_lds_bytes(const ks_batch* b)
-{
-    const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
-    return xc_lds_bytes_for(es, xc_block_points(b), b->max_np);
-}
+size_t xc_lds_bytes(const ks_batch* b) { return xc_shape(b).lds; }
 
 }  // namespace ks

@@ -39,12 +39,15 @@ ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out);
 ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
                     bool track);
 size_t jk_lds_bytes(const ks_batch* b);
+bool jk_acc_fp64(const ks_batch* b);
 
 // grid and XC (k_xc.hip)
 ks_status launch_grid(ks_batch* b);
 ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active);
 size_t xc_lds_bytes(const ks_batch* b);
 int xc_block_points(const ks_batch* b);
+struct XcShape { int bp = 32, nw = 8; size_t lds = 0; };
+XcShape xc_shape(const ks_batch* b);
 
 // SCF steps (k_scf.hip)
 ks_status launch_fock(ks_batch* b, const double* P, const double* J, const double* K, const double* Vxc,

@@ -42,7 +42,8 @@ class Options(C.Structure):
     _fields_ = [("xc", C.c_int), ("prec", C.c_int), ("n_rad", C.c_int), ("n_theta", C.c_int),
                 ("n_phi", C.c_int), ("e_tol", C.c_double), ("comm_tol", C.c_double),
                 ("max_iter", C.c_int), ("diis_space", C.c_int), ("jk_chunks", C.c_int),
-                ("xc_chunks", C.c_int), ("guess", C.c_int)]
+                ("xc_chunks", C.c_int), ("guess", C.c_int), ("xc_points", C.c_int),
+                ("xc_waves", C.c_int)]
 
 
 _lib = None
