@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=0, help="molecules in the oracle sample (0 = one per thread)")
     p.add_argument("--jk-chunks", type=int, default=0)
     p.add_argument("--xc-chunks", type=int, default=0)
+    p.add_argument("--serve-requests", type=int, default=512, help="serving leg requests (0 = skip)")
     return p.parse_args()
 
 
@@ -94,6 +95,56 @@ def run_path(ks, torch, mols, prec, args, steps, warmup):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     return total, times, last
+
+
+def serve_run(ks, reqs, arrivals, prec):
+    """Drive a ks.Server with requests arriving at the given times (s); returns
+    (wall seconds, latencies from scheduled arrival to observed completion)."""
+    srv = ks.Server(prec=prec)
+    n = len(reqs)
+    lat = np.zeros(n)
+    pending = {}
+    nxt, done = 0, 0
+    t0 = time.perf_counter()
+    while done < n:
+        t = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= t:
+            z, x = reqs[nxt]
+            pending[srv.submit(z, x)] = nxt
+            nxt += 1
+        st = srv.stats()
+        if st["queued"] == 0 and st["resident"] == 0:
+            if nxt < n:
+                time.sleep(max(0.0, min(0.01, arrivals[nxt] - (time.perf_counter() - t0))))
+            continue
+        if srv.progress() > 0:
+            now = time.perf_counter() - t0
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is not None:
+                    i = pending.pop(tk)
+                    lat[i] = now - arrivals[i]
+                    done += 1
+    wall = time.perf_counter() - t0
+    srv.close()
+    return wall, lat
+
+
+def serving_leg(ks, args):
+    """configs[3]-shaped serving: 3-11 heavy atoms, mixed precision; saturated
+    throughput first, then Poisson arrivals at 0.8 x that rate."""
+    from paper_2311_01135_amd import molgen
+    n = args.serve_requests
+    reqs = molgen.batch(n, 3, (3, 11))
+    wall_sat, _ = serve_run(ks, reqs, np.zeros(n), ks.KS_MIXED)
+    sat = n / wall_sat
+    lam = 0.8 * sat
+    rng = np.random.default_rng(3)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
+    wall, lat = serve_run(ks, reqs, arrivals, ks.KS_MIXED)
+    return dict(requests=n, heavy_atoms="3-11", precision="mixed", saturated_solves_per_s=sat,
+                arrival_rate_per_s=lam, solves_per_s=n / wall, p50_latency_s=float(np.percentile(lat, 50)),
+                p99_latency_s=float(np.percentile(lat, 99)), max_latency_s=float(lat.max()))
 
 
 def cpu_baseline(mols, args):
@@ -180,6 +231,13 @@ def main():
                 frac=achieved / PEAK[dtype], traffic=None,
                 flops_per_launch=fl / max(1, xc_launches), avg_launch_ms=xc_ms, launches=xc_launches)
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(ks, args)
+        print("serving: %.1f solves/s saturated, lambda %.1f/s, p50 %.3f s p99 %.3f s"
+              % (serving["saturated_solves_per_s"], serving["arrival_rate_per_s"], serving["p50_latency_s"],
+                 serving["p99_latency_s"]), file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu, _ = cpu_baseline(mols, args)
@@ -213,6 +271,7 @@ def main():
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "fp64": fp64,
         "accuracy": acc,
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

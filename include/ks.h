@@ -195,6 +195,48 @@ void ks_batch_destroy(ks_batch* b);
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* ks_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of SCF requests.  The paper generates its
+ * dataset as a stream of independent molecules (section 4); here requests of
+ * uneven size arrive at any time, are admitted while the HBM budget allows,
+ * keep their density, Fock matrix and DIIS history on the device, advance one
+ * SCF iteration per ks_server_progress call together with every other
+ * resident molecule, and retire as soon as they converge.
+ * ------------------------------------------------------------------------ */
+typedef struct ks_server ks_server;
+
+/* opt as for ks_batch_create (NULL = defaults; jk_chunks / xc_chunks of 0
+ * become 8 / 16 so that a molecule's arithmetic is the same in any batch);
+ * hbm_budget in bytes (0 = 80% of the free device memory); max_batch caps
+ * the molecules admitted per admission wave (<= 0: 64). */
+ks_status ks_server_create(const ks_options* opt, size_t hbm_budget, int max_batch, ks_server** out);
+
+/* Queues one molecule (Angstrom, charge) and returns its ticket.  The
+ * molecule is validated here (KS_EINVAL / KS_EUNSUPPORTED as for
+ * ks_batch_create); nothing runs on the device until ks_server_progress. */
+ks_status ks_server_submit(ks_server* s, int n_atoms, const int* Z, const double* xyz_angstrom, int charge,
+                           long* ticket);
+
+/* One scheduling round: one SCF iteration of every resident molecule (each
+ * resident batch on its own stream), admission of queued requests while the
+ * budget allows (their integrals and grid are built while the iterations
+ * run), then retirement of converged molecules and release of empty batches.
+ * *n_finished = requests completed in this call. */
+ks_status ks_server_progress(ks_server* s, int* n_finished);
+
+/* Result of a ticket: KS_OK when finished (outputs filled; latency_s from
+ * submit to retirement), KS_ESTATE while queued or resident, the admission
+ * error when the request was rejected.  Output pointers may be NULL. */
+ks_status ks_server_poll(const ks_server* s, long ticket, double* E, double* homo, double* lumo, double* gap,
+                         int* status, int* n_iter, double* latency_s);
+
+/* Queue length, resident (still iterating) molecules, completed requests and
+ * device bytes held by resident batches. */
+ks_status ks_server_stats(const ks_server* s, int* queued, int* resident, long* done, size_t* bytes_in_use);
+
+/* Releases every resident batch.  NULL-safe. */
+void ks_server_destroy(ks_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libks.so")
-SOURCES = ["abi.hip", "k_ints.hip", "k_jk.hip", "k_xc.hip", "k_scf.hip"]
+SOURCES = ["abi.hip", "server.hip", "k_ints.hip", "k_jk.hip", "k_xc.hip", "k_scf.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -178,6 +178,7 @@ static ks_status dev_alloc(ks_batch* b, T** p, size_t n)
         return e == hipErrorOutOfMemory ? KS_ENOMEM : KS_EDEVICE;
     }
     b->allocs.push_back(q);
+    b->alloc_bytes += n * sizeof(T);
     *p = (T*)q;
     return KS_OK;
 }
@@ -646,9 +647,14 @@ ks_status fock_build(ks_batch* b, const void* Pin, void* F, double* E_terms)
     return KS_OK;
 }
 
-ks_status scf_step(ks_batch* b, int* n_active)
+}  // extern "C"
+
+namespace ks {
+
+// One SCF iteration queued on the batch stream, without waiting: the count of
+// still-active molecules lands in pinned host memory (read by step_finish).
+ks_status step_launch(ks_batch* b)
 {
-    CHECK_B(b);
     ks_status st;
     if (!b->eri_done && (st = eri_build(b))) return st;
     // mixed path: incremental J/K from P - Pprev (FP32 digest, FP64 accumulation)
@@ -659,10 +665,29 @@ ks_status scf_step(ks_batch* b, int* n_active)
     if ((st = launch_iteration_tail(b))) return st;
     if ((st = launch_count_active(b))) return st;
     KS_HIP(hipMemcpyAsync(b->h_nactive, b->d_nactive, sizeof(int), hipMemcpyDeviceToHost, b->stream));
-    KS_HIP(hipStreamSynchronize(b->stream));
     b->iter++;
+    return KS_OK;
+}
+
+ks_status step_finish(ks_batch* b, int* n_active)
+{
+    KS_HIP(hipStreamSynchronize(b->stream));
     if (n_active) *n_active = *b->h_nactive;
     return KS_OK;
+}
+
+size_t batch_device_bytes(const ks_batch* b) { return b->alloc_bytes; }
+
+}  // namespace ks
+
+extern "C" {
+
+ks_status scf_step(ks_batch* b, int* n_active)
+{
+    CHECK_B(b);
+    ks_status st = step_launch(b);
+    if (st) return st;
+    return step_finish(b, n_active);
 }
 
 ks_status scf_solve(ks_batch* b)

@@ -57,4 +57,9 @@ ks_status launch_guess(ks_batch* b);
 ks_status launch_iteration_tail(ks_batch* b);
 ks_status launch_count_active(ks_batch* b);
 
+// SCF driver pieces (abi.hip) used by the server
+ks_status step_launch(ks_batch* b);
+ks_status step_finish(ks_batch* b, int* n_active);
+size_t batch_device_bytes(const ks_batch* b);
+
 }  // namespace ks

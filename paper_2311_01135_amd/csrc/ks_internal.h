@@ -126,6 +126,7 @@ struct ks_batch {
 
     // device memory (owned)
     std::vector<void*> allocs;
+    size_t alloc_bytes = 0;         // device bytes held by this batch
     ks::MolDesc* d_mol = nullptr;
     ks::MolState* d_state = nullptr;
     ks::Shell* d_shells = nullptr;

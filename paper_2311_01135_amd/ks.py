@@ -29,7 +29,8 @@ EXPORTS = ["ks_default_options", "ks_batch_create", "ks_batch_sizes", "ks_batch_
            "eri_build", "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "ks_get_result",
            "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence", "ks_kernel_times",
            "ks_kernel_counts", "ks_set_timing",
-           "ks_batch_destroy", "ks_last_error"]
+           "ks_batch_destroy", "ks_last_error", "ks_server_create", "ks_server_submit",
+           "ks_server_progress", "ks_server_poll", "ks_server_stats", "ks_server_destroy"]
 
 
 class KsError(RuntimeError):
@@ -81,6 +82,15 @@ def load():
     L.ks_get_convergence.restype = C.c_int
     L.ks_batch_destroy.argtypes = [vp]
     L.ks_batch_destroy.restype = None
+    L.ks_server_create.argtypes = [C.POINTER(Options), C.c_size_t, C.c_int, C.POINTER(vp)]
+    L.ks_server_submit.argtypes = [vp, C.c_int, ip, dp, C.c_int, lp]
+    L.ks_server_progress.argtypes = [vp, ip]
+    L.ks_server_poll.argtypes = [vp, C.c_long, dp, dp, dp, dp, ip, ip, dp]
+    L.ks_server_stats.argtypes = [vp, ip, ip, lp, C.POINTER(C.c_size_t)]
+    L.ks_server_destroy.argtypes = [vp]
+    L.ks_server_destroy.restype = None
+    for name in ("ks_server_create", "ks_server_submit", "ks_server_progress", "ks_server_poll", "ks_server_stats"):
+        getattr(L, name).restype = C.c_int
     L.ks_last_error.restype = C.c_char_p
     for name in ("ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup", "eri_build",
                  "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "ks_get_result",
@@ -243,3 +253,58 @@ class Batch:
     def unpack(self, t):
         a = t.detach().cpu().numpy()
         return [a[self.mat_off[m]:self.mat_off[m + 1]].reshape(self.nbf[m], self.nbf[m]) for m in range(self.n_mol)]
+
+
+class Server:
+    """Continuous-batching SCF server (ks_server_*)."""
+
+    def __init__(self, hbm_budget: int = 0, max_batch: int = 64, **options):
+        L = load()
+        self.opt = default_options(**options)
+        h = C.c_void_p()
+        _check(L.ks_server_create(C.byref(self.opt), C.c_size_t(hbm_budget), max_batch, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.ks_server_destroy(h)
+        self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, Z, xyz, charge: int = 0) -> int:
+        Z = np.ascontiguousarray(np.asarray(Z, dtype=np.int32))
+        xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1))
+        t = C.c_long()
+        _check(load().ks_server_submit(self.h, len(Z), _iptr(Z), _dptr(xyz), charge, C.byref(t)))
+        return t.value
+
+    def progress(self) -> int:
+        n = C.c_int()
+        _check(load().ks_server_progress(self.h, C.byref(n)))
+        return n.value
+
+    def poll(self, ticket):
+        """dict of results when finished, None while pending."""
+        E, homo, lumo, gap, lat = (C.c_double() for _ in range(5))
+        st, it = C.c_int(), C.c_int()
+        rc = load().ks_server_poll(self.h, ticket, C.byref(E), C.byref(homo), C.byref(lumo), C.byref(gap),
+                                   C.byref(st), C.byref(it), C.byref(lat))
+        if rc == -6:
+            return None
+        _check(rc)
+        return dict(E=E.value, homo=homo.value, lumo=lumo.value, gap=gap.value, status=st.value,
+                    n_iter=it.value, latency=lat.value)
+
+    def stats(self):
+        q, r, d, by = C.c_int(), C.c_int(), C.c_long(), C.c_size_t()
+        _check(load().ks_server_stats(self.h, C.byref(q), C.byref(r), C.byref(d), C.byref(by)))
+        return dict(queued=q.value, resident=r.value, done=d.value, bytes=by.value)

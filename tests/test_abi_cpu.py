@@ -84,3 +84,23 @@ def test_null_handle_calls(lib):
     assert lib.eri_build(None) == -1
     assert lib.scf_solve(None) == -1
     lib.ks_batch_destroy(None)
+
+
+def test_server_host_paths(lib):
+    """Submission validation and polling of a queued ticket need no device."""
+    from paper_2311_01135_amd import ks, molgen
+    with ks.Server(hbm_budget=1 << 30) as s:
+        with pytest.raises(ks.KsError) as e:
+            s.submit([1], [[0, 0, 0]])                          # odd electron count
+        assert e.value.status == -1
+        with pytest.raises(ks.KsError):
+            s.submit([2, 2], [[0, 0, 0], [1, 0, 0]])            # unsupported element
+        z, x = molgen.water(0)
+        t0 = s.submit(z, x)
+        t1 = s.submit(z, x + 0.01)
+        assert (t0, t1) == (0, 1)
+        assert s.poll(t0) is None                               # queued, not run
+        st = s.stats()
+        assert st["queued"] == 2 and st["resident"] == 0 and st["done"] == 0
+        with pytest.raises(ks.KsError):
+            s.poll(7)

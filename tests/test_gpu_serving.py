@@ -1,0 +1,78 @@
+"""Continuous-batching server on the GPU: every result is the same alone and
+in the mix (FP64: |dE| <= 1e-10 Ha, |d gap| <= 1e-10 Ha, same iteration
+count; mixed: |dE|, |d gap| <= 1e-6 Ha), under staggered arrivals and an HBM
+budget small enough to force several admission waves and mid-flight retires."""
+import numpy as np
+import pytest
+
+from paper_2311_01135_amd import molgen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_01135_amd import ks as K
+    K.load()
+    return K
+
+
+def _mols():
+    out = [molgen.water(1)]
+    out += [molgen.tree(n, 13, i) for i, n in enumerate((1, 2, 3, 4, 5))]
+    out += [molgen.tree(9, 13, 10), molgen.tree(10, 13, 11)]
+    return out
+
+
+def _alone(ks, mols, **opt):
+    res = []
+    for z, x in mols:
+        with ks.Batch([(z, x)], jk_chunks=8, xc_chunks=16, **opt) as b:
+            b.scf_solve()
+            res.append(b.result(0))
+    return res
+
+
+def _serve(ks, mols, budget, **opt):
+    out = {}
+    with ks.Server(hbm_budget=budget, max_batch=3, **opt) as s:
+        tickets = [s.submit(z, x) for z, x in mols[:3]]
+        for _ in range(2):
+            s.progress()
+        tickets += [s.submit(z, x) for z, x in mols[3:]]
+        peak = 0
+        for _ in range(400):
+            s.progress()
+            st = s.stats()
+            peak = max(peak, st["bytes"])
+            if st["done"] == len(mols):
+                break
+        for i, t in enumerate(tickets):
+            out[i] = s.poll(t)
+        assert s.stats()["bytes"] == 0          # every batch released
+    return [out[i] for i in range(len(mols))], peak
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_alone_equals_mix(ks, prec):
+    mols = _mols()
+    alone = _alone(ks, mols, prec=prec)
+    served, peak = _serve(ks, mols, budget=600 << 20, prec=prec)
+    tol = 1e-10 if prec == 0 else 1e-6
+    for a, s in zip(alone, served):
+        assert s is not None and s["status"] == 1 and a["status"] == 1
+        assert abs(a["E"] - s["E"]) <= tol, (a["E"], s["E"])
+        assert abs(a["gap"] - s["gap"]) <= tol
+        if prec == 0:
+            assert a["n_iter"] == s["n_iter"]
+        assert s["latency"] > 0
+
+
+def test_tiny_budget_serialises(ks):
+    """A budget below one molecule still admits one molecule at a time."""
+    mols = _mols()[:4]
+    served, peak = _serve(ks, mols, budget=1 << 20)
+    assert all(r is not None and r["status"] == 1 for r in served)
