@@ -62,7 +62,9 @@ def xc_flops(nbf, ngrid, niter):
 
 
 def solve_batch(ks, mols, prec, timing, args):
+    from paper_2311_01135_amd import autotune, molgen
     kw = dict(prec=prec)
+    kw.update(autotune.tuned_options(prec, [molgen.nbf_sto3g(z) for z, _ in mols]))
     if args.jk_chunks:
         kw["jk_chunks"] = args.jk_chunks
     if args.xc_chunks:

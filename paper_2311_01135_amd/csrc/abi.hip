@@ -469,7 +469,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     if ((st = upload(b, &b->d_xc_first, xc_first))) return st;
     for (int c = 0; c < 3; c++) {
         if ((st = upload(b, &b->d_pairs[c], pairs[c]))) return st;
-        if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair))) return st;
+        if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair * 5))) return st;
     }
     for (int c = 0; c < kNClass; c++)
         if ((st = upload(b, &b->d_qoff[c], qprefix[c]))) return st;
@@ -477,7 +477,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     std::memset(s0.data(), 0, sizeof(MolState) * n_mol);
     if ((st = upload(b, &b->d_state, s0))) return st;
     double** mats[] = {&b->d_S, &b->d_T, &b->d_V, &b->d_H, &b->d_X, &b->d_F, &b->d_P,
-                       &b->d_J, &b->d_K, &b->d_Vxc, &b->d_Fp, &b->d_C, &b->d_Pprev};
+                       &b->d_J, &b->d_K, &b->d_Vxc, &b->d_Fp, &b->d_C, &b->d_Pprev, &b->d_Cp};
     for (double** p : mats)
         if ((st = dev_alloc(b, p, (size_t)b->nmat))) return st;
     if ((st = dev_alloc(b, &b->d_eps, (size_t)ao0))) return st;
@@ -497,12 +497,14 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     if ((st = dev_alloc(b, &b->d_exc, (size_t)n_mol))) return st;
     if ((st = dev_alloc(b, &b->d_nactive, 1))) return st;
     if ((st = dev_alloc(b, &b->d_eterms, 6 * (size_t)n_mol))) return st;
+    if ((st = dev_alloc(b, &b->d_have_warm, (size_t)n_mol))) return st;
     KS_HIP(hipHostMalloc((void**)&b->h_nactive, sizeof(int), hipHostMallocDefault));
     KS_HIP(hipMemsetAsync(b->d_Vxc, 0, sizeof(double) * b->nmat, b->stream));
     KS_HIP(hipMemsetAsync(b->d_J, 0, sizeof(double) * b->nmat, b->stream));
     KS_HIP(hipMemsetAsync(b->d_K, 0, sizeof(double) * b->nmat, b->stream));
     KS_HIP(hipMemsetAsync(b->d_Pprev, 0, sizeof(double) * b->nmat, b->stream));
     KS_HIP(hipMemsetAsync(b->d_exc, 0, sizeof(double) * n_mol, b->stream));
+    KS_HIP(hipMemsetAsync(b->d_have_warm, 0, sizeof(int) * n_mol, b->stream));
     KS_HIP(hipStreamSynchronize(b->stream));
     return KS_OK;
 }

@@ -129,6 +129,14 @@ __device__ __forceinline__ void hermite_E(R XPA, R XPB, R i2p, R (&e)[4][3])
 // Cartesian exponent of component c (0..2 for p, s has 0) along direction d.
 __host__ __device__ constexpr int lexp(int L, int c, int d) { return (L == 1 && c == d) ? 1 : 0; }
 
+// Read-only view of one pair in a field-major primitive-pair table.
+struct PairView {
+    const double* t;
+    long n;
+    int i;
+    __device__ __forceinline__ double get(int f, int k) const { return t[((size_t)f * kNPrimPair + k) * n + i]; }
+};
+
 // ---------------------------------------------------------------------------
 // contracted shell quartet (ab|cd), McMurchie-Davidson:
 // (ab|cd) = 2 pi^(5/2) / (p q sqrt(p+q)) K_ab K_cd
@@ -136,8 +144,7 @@ __host__ __device__ constexpr int lexp(int L, int c, int d) { return (L == 1 && 
 // ---------------------------------------------------------------------------
 template <int LA, int LB, int LC, int LD, typename R>
 __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, const Shell& sc, const Shell& sd,
-                                            const PairPrim* __restrict__ ppb, const PairPrim* __restrict__ ppk,
-                                            const R* __restrict__ tab, R* acc)
+                                            const PairView& vb, const PairView& vk, const R* __restrict__ tab, R* acc)
 {
     constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
@@ -145,22 +152,22 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
 #pragma unroll
     for (int i = 0; i < NA * NB * NC * ND; i++) acc[i] = R(0);
     for (int ip = 0; ip < kNPrimPair; ip++) {
-        const PairPrim bp = ppb[ip];
-        const R p = R(bp.p), Kb = R(bp.K);
+        const double bP[3] = {vb.get(1, ip), vb.get(2, ip), vb.get(3, ip)};
+        const R p = R(vb.get(0, ip)), Kb = R(vb.get(4, ip));
         if (Kb == R(0)) continue;
         R eb[3][4][3];
         const R i2p = R(0.5) / p;
 #pragma unroll
-        for (int d = 0; d < 3; d++) hermite_E<R>(R(bp.P[d] - sa.A[d]), R(bp.P[d] - sb.A[d]), i2p, eb[d]);
+        for (int d = 0; d < 3; d++) hermite_E<R>(R(bP[d] - sa.A[d]), R(bP[d] - sb.A[d]), i2p, eb[d]);
         for (int jp = 0; jp < kNPrimPair; jp++) {
-            const PairPrim kp = ppk[jp];
-            const R q = R(kp.p), Kk = R(kp.K);
+            const double kP[3] = {vk.get(1, jp), vk.get(2, jp), vk.get(3, jp)};
+            const R q = R(vk.get(0, jp)), Kk = R(vk.get(4, jp));
             if (Kk == R(0)) continue;
             R ek[3][4][3];
             const R i2q = R(0.5) / q;
 #pragma unroll
-            for (int d = 0; d < 3; d++) hermite_E<R>(R(kp.P[d] - sc.A[d]), R(kp.P[d] - sd.A[d]), i2q, ek[d]);
-            const R PQx = R(bp.P[0] - kp.P[0]), PQy = R(bp.P[1] - kp.P[1]), PQz = R(bp.P[2] - kp.P[2]);
+            for (int d = 0; d < 3; d++) hermite_E<R>(R(kP[d] - sc.A[d]), R(kP[d] - sd.A[d]), i2q, ek[d]);
+            const R PQx = R(bP[0] - kP[0]), PQy = R(bP[1] - kP[1]), PQz = R(bP[2] - kP[2]);
             const R pq = p + q, alpha = p * q / pq;
             const R T = alpha * (PQx * PQx + PQy * PQy + PQz * PQz);
             R F[L + 1];
@@ -266,8 +273,9 @@ struct EriArgs {
     const Shell* shells;
     const Pair* pb;         // bra pair class list
     const Pair* pk;
-    const PairPrim* ppb;
-    const PairPrim* ppk;
+    const double* ppb;      // primitive-pair tables [5][9][npair] of the bra / ket class
+    const double* ppk;
+    long npb, npk;
     const void* tab;
     void* out;              // [ncomp][nq]
 };
@@ -288,16 +296,18 @@ __global__ __launch_bounds__(128) void eri_class_kernel(EriArgs g)
     const Pair P1 = g.pb[ib], P2 = g.pk[ik];
     const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
     R acc[NCOMP];
-    eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, g.ppb + (size_t)ib * kNPrimPair, g.ppk + (size_t)ik * kNPrimPair,
-                                   (const R*)g.tab, acc);
+    const PairView vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
+    eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, (const R*)g.tab, acc);
     S* out = (S*)g.out;
 #pragma unroll
     for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
 }
 
-// Primitive-pair tables of every shell pair of one pair class.
+// Primitive-pair tables of every shell pair of one pair class, stored
+// field-major [f][k][pair] (f = p, Px, Py, Pz, K; k = primitive pair) so that
+// lanes working on consecutive pairs load consecutive addresses.
 __global__ void pair_kernel(const Shell* __restrict__ shells, const Pair* __restrict__ pairs, long npair,
-                            PairPrim* __restrict__ out)
+                            double* __restrict__ out)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npair * kNPrimPair) return;
@@ -308,14 +318,12 @@ __global__ void pair_kernel(const Shell* __restrict__ shells, const Pair* __rest
     const Shell& B = shells[pr.sb];
     const double a = A.a[ka], b = B.a[kb], p = a + b;
     double r2 = 0.0;
-    PairPrim o;
-    o.p = p;
     for (int d = 0; d < 3; d++) {
-        o.P[d] = (a * A.A[d] + b * B.A[d]) / p;
+        out[((size_t)(1 + d) * kNPrimPair + k) * npair + ip] = (a * A.A[d] + b * B.A[d]) / p;
         r2 += (A.A[d] - B.A[d]) * (A.A[d] - B.A[d]);
     }
-    o.K = A.c[ka] * B.c[kb] * exp(-a * b / p * r2);
-    out[t] = o;
+    out[(size_t)k * npair + ip] = p;
+    out[((size_t)4 * kNPrimPair + k) * npair + ip] = A.c[ka] * B.c[kb] * exp(-a * b / p * r2);
 }
 
 // ---------------------------------------------------------------------------
@@ -474,6 +482,8 @@ static ks_status launch_class(ks_batch* b, int c)
     g.pk = b->d_pairs[class_ket(c)];
     g.ppb = b->d_pp[class_bra(c)];
     g.ppk = b->d_pp[class_ket(c)];
+    g.npb = b->npairs[class_bra(c)];
+    g.npk = b->npairs[class_ket(c)];
     g.tab = std::is_same<R, double>::value ? (const void*)b->d_boys : (const void*)b->d_boys_f;
     g.out = b->d_eri[c];
     const long nb = (g.nq + 127) / 128;

@@ -301,10 +301,16 @@ __global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const doub
 // LDS.  Rotation: theta = (a_qq - a_pp)/(2 a_pq), t = sgn(theta)/(|theta| +
 // sqrt(theta^2 + 1)), c = 1/sqrt(1 + t^2), s = t c; rows then columns.
 // Output: ascending eigenvalues vals[N], eigenvectors as columns of vecs.
+// Warm start (SCF iterations): with the previous iteration's eigenvectors W
+// (warm), the rotations start from V = W on A = W^T F' W, which is nearly
+// diagonal close to self-consistency, so few sweeps remain; the sorted
+// vectors are kept in `keep` for the next iteration.  tmp: N^2 scratch.
 __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __restrict__ mols,
                                                            const MolState* __restrict__ state, int only_active,
                                                            const double* __restrict__ src, double* __restrict__ vecs,
-                                                           double* __restrict__ vals)
+                                                           double* __restrict__ vals, const double* __restrict__ warm,
+                                                           double* __restrict__ keep, double* __restrict__ tmp,
+                                                           int* __restrict__ have_warm)
 {
     const int m = blockIdx.x;
     if (only_active && state[m].status != KS_MOL_ACTIVE) return;
@@ -318,11 +324,38 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
     __shared__ double red[2 * kScfThreads / 64];
     __shared__ int rank_of[kMaxNbf];
     const double* a0 = src + md.mat0;
+    const bool use_warm = warm && have_warm[m];
     for (int t = threadIdx.x; t < NN; t += blockDim.x) {
         A[t] = a0[t];
-        Vv[t] = (t / N == t % N) ? 1.0 : 0.0;
+        Vv[t] = use_warm ? warm[md.mat0 + t] : ((t / N == t % N) ? 1.0 : 0.0);
     }
     __syncthreads();
+    if (use_warm) {
+        double* T = tmp + md.mat0;
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) {      // T = F' W
+            const int i = t / N, j = t % N;
+            double s = 0.0;
+            for (int k = 0; k < N; k++) s += A[i * N + k] * Vv[k * N + j];
+            T[t] = s;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) {      // A = W^T T
+            const int i = t / N, j = t % N;
+            double s = 0.0;
+            for (int k = 0; k < N; k++) s += Vv[k * N + i] * T[k * N + j];
+            A[t] = s;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) {      // symmetrise
+            const int i = t / N, j = t % N;
+            if (i < j) {
+                const double s = 0.5 * (A[i * N + j] + A[j * N + i]);
+                A[i * N + j] = s;
+                A[j * N + i] = s;
+            }
+        }
+        __syncthreads();
+    }
     const int nn = N + (N & 1), half = nn / 2;
     for (int sweep = 0; sweep < 60; sweep++) {
         double off = 0.0, oc = 0.0, tot = 0.0, tc = 0.0;
@@ -393,8 +426,10 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
     for (int t = threadIdx.x; t < NN; t += blockDim.x) {
         const int i = t / N, k = t % N;   // component i of eigenvector k
         vecs[md.mat0 + i * N + rank_of[k]] = Vv[i * N + k];
+        if (keep) keep[md.mat0 + i * N + rank_of[k]] = Vv[i * N + k];
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) vals[md.ao0 + rank_of[i]] = A[i * N + i];
+    if (keep && threadIdx.x == 0) have_warm[m] = 1;
 }
 
 // X = U s^-1/2 U^T from eigh(S) (vectors in C, values in eps); flags near-singular S.
@@ -484,12 +519,16 @@ static size_t eigh_lds(const ks_batch* b)
     return 2 * sizeof(double) * (size_t)maxn * maxn;
 }
 
-static ks_status run_eigh(ks_batch* b, bool only_active, const double* src, double* vecs, double* vals)
+// warm == nullptr: cold start from the identity.  Otherwise warm/keep hold the
+// previous eigenvectors (read when have_warm[m], then overwritten).
+static ks_status run_eigh(ks_batch* b, bool only_active, const double* src, double* vecs, double* vals,
+                          double* warm = nullptr)
 {
     const size_t lds = eigh_lds(b);
     KS_HIP(hipFuncSetAttribute((const void*)eigh_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(eigh_kernel, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, b->d_mol, b->d_state,
-                       (int)only_active, src, vecs, vals);
+                       (int)only_active, src, vecs, vals, (const double*)warm, warm, warm ? b->d_work : nullptr,
+                       warm ? b->d_have_warm : nullptr);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
@@ -547,7 +586,7 @@ ks_status launch_iteration_tail(ks_batch* b)
     }
     {
         KTimer tm(b, "eigh");
-        ks_status st = run_eigh(b, true, b->d_Fp, b->d_Fp, b->d_eps);
+        ks_status st = run_eigh(b, true, b->d_Fp, b->d_Fp, b->d_eps, b->d_Cp);
         if (st) return st;
     }
     {

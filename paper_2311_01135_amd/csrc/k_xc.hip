@@ -38,9 +38,18 @@ __global__ __launch_bounds__(128) void grid_kernel(const MolDesc* __restrict__ m
     const MolDesc md = mols[m];
     const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
     extern __shared__ double smem_grid[];
+    const int na = md.natom;
     double* Ra = smem_grid;                       // [natom][3]
-    double* dist = smem_grid + 3 * md.natom;     // [natom][blockDim]
-    for (int i = threadIdx.x; i < 3 * md.natom; i += blockDim.x) Ra[i] = Rat[3 * md.atom0 + i];
+    double* invR = Ra + 3 * na;                   // [natom][natom]: 1/|R_a - R_c|
+    double* dist = invR + na * na;                // [natom][blockDim]
+    for (int i = threadIdx.x; i < 3 * na; i += blockDim.x) Ra[i] = Rat[3 * md.atom0 + i];
+    for (int i = threadIdx.x; i < na * na; i += blockDim.x) {
+        const int a = i / na, c = i % na;
+        const double* pa = Rat + 3 * (md.atom0 + a);
+        const double* pc = Rat + 3 * (md.atom0 + c);
+        const double dx = pa[0] - pc[0], dy = pa[1] - pc[1], dz = pa[2] - pc[2];
+        invR[i] = a == c ? 0.0 : 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    }
     __syncthreads();
     if (l >= md.ngrid) return;
     const int per_atom = nrad * nth * nph;
@@ -61,14 +70,13 @@ __global__ __launch_bounds__(128) void grid_kernel(const MolDesc* __restrict__ m
         dist[a * bs + t] = sqrt(dx * dx + dy * dy + dz * dz);
     }
     double num = 0.0, den = 0.0;
-    for (int a = 0; a < md.natom; a++) {
+    for (int a = 0; a < na; a++) {
         const double ra = dist[a * bs + t];
+        const double* ir = invR + a * na;
         double Pa = 1.0;
-        for (int c = 0; c < md.natom && Pa > 0.0; c++) {
+        for (int c = 0; c < na && Pa > 0.0; c++) {
             if (c == a) continue;
-            const double dx = Ra[3 * a] - Ra[3 * c], dy = Ra[3 * a + 1] - Ra[3 * c + 1], dz = Ra[3 * a + 2] - Ra[3 * c + 2];
-            const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-            Pa *= becke_s((ra - dist[c * bs + t]) * inv);
+            Pa *= becke_s((ra - dist[c * bs + t]) * ir[c]);
         }
         if (a == A) num = Pa;
         den += Pa;
@@ -91,7 +99,7 @@ ks_status launch_grid(ks_batch* b)
         maxat = std::max(maxat, m.natom);
     }
     const int bs = 128;
-    const size_t lds = sizeof(double) * (3 * maxat + (size_t)maxat * bs);
+    const size_t lds = sizeof(double) * (3 * maxat + (size_t)maxat * maxat + (size_t)maxat * bs);
     KS_HIP(hipFuncSetAttribute((const void*)grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, b->stream,
                        b->d_mol, b->d_R, b->d_radial, b->d_ang, b->opt.n_rad, b->opt.n_theta, b->opt.n_phi, b->d_grid);

@@ -44,10 +44,8 @@ struct Shell {
 };
 
 // Primitive-pair data of a shell pair (McMurchie-Davidson Gaussian product):
-// p = a + b, P = (a A + b B)/p, K = c_a c_b exp(-a b/p |A-B|^2).
-struct PairPrim {
-    double p, P[3], K;
-};
+// p = a + b, P = (a A + b B)/p, K = c_a c_b exp(-a b/p |A-B|^2), stored
+// field-major over the pairs of a pair class (see pair_kernel).
 
 // Shell pair (global shell indices); sa carries the higher angular momentum.
 struct Pair {
@@ -134,7 +132,7 @@ struct ks_batch {
     double* d_R = nullptr;          // atom positions (bohr)
     double* d_Zc = nullptr;         // atom charges
     ks::Pair* d_pairs[3] = {nullptr, nullptr, nullptr};
-    ks::PairPrim* d_pp[3] = {nullptr, nullptr, nullptr};
+    double* d_pp[3] = {nullptr, nullptr, nullptr};   // [5][9][npair] primitive-pair tables
     long* d_qoff[ks::kNClass] = {};  // prefix over molecules (n_mol + 1)
     void* d_eri[ks::kNClass] = {};   // component-major, FP64 or FP32
     double* d_boys = nullptr;
@@ -148,6 +146,8 @@ struct ks_batch {
     double *d_Fp = nullptr, *d_C = nullptr, *d_eps = nullptr, *d_work = nullptr;
     double *d_Fh = nullptr, *d_Eh = nullptr;    // DIIS history (diis_space * nmat each)
     double* d_Pprev = nullptr;      // density the resident J, K were built from (mixed path)
+    double* d_Cp = nullptr;         // previous iteration's eigenvectors of F' (eigensolver warm start)
+    int* d_have_warm = nullptr;     // [n_mol] d_Cp holds vectors for this molecule
     void* d_Pt = nullptr;           // padded density in the XC compute type (np^2 per molecule)
     long* d_ptoff = nullptr;        // offsets of d_Pt blocks
     long npt_total = 0;

@@ -79,7 +79,7 @@ static size_t estimate_bytes(const ks_options& o, int natom, int nbf)
     const double eri = 0.5 * npair * npair * 1.3 * es;
     const double grid = (double)natom * o.n_rad * o.n_theta * o.n_phi * 32.0;
     const double np = std::ceil(nbf / 16.0) * 16.0;
-    const double mats = (16.0 + 2.0 * o.diis_space) * nbf * nbf * 8.0;
+    const double mats = (18.0 + 2.0 * o.diis_space) * nbf * nbf * 8.0;
     const double parts = (2.0 * 8.0 * np * np * 8.0) + 16.0 * np * np * es;
     return (size_t)(eri + grid + mats + parts) + (1u << 20);
 }
