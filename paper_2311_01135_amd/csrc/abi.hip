@@ -410,6 +410,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         grid0 += md.ngrid;
         ao0 += nbf;
         b->max_np = std::max(b->max_np, md.np);
+        b->max_nshell = std::max(b->max_nshell, md.nshell);
     }
     b->nmat = mat0;
     b->ngrid = grid0;

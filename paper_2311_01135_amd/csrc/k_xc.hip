@@ -110,12 +110,13 @@ ks_status launch_grid(ks_batch* b)
 // ---------------------------------------------------------------------------
 // B3LYP, closed shell: energy per volume e and v_rho = de/drho,
 // v_sigma = de/dsigma (sigma = |grad rho|^2).
-// e = 0.08 Slater + 0.72 B88 + 0.19 VWN + 0.81 LYP
+// e = 0.08 Slater + 0.72 B88 + 0.19 VWN + 0.81 LYP, evaluated as three
+// weighted parts (exchange, VWN, LYP) that the XC kernel hands to three
+// wavefronts; part k adds its e, v_rho, v_sigma.
 // ---------------------------------------------------------------------------
 template <typename F>
-__device__ __forceinline__ void b3lyp(F rho, F sigma, int vwn5, F& e, F& vr, F& vs)
+__device__ __forceinline__ void b3lyp_exchange(F rho, F sigma, F& e, F& vr, F& vs)
 {
-    const F pi = F(kPi);
     const F r13 = cbrt(rho);
     // Slater exchange, -(3/4)(3/pi)^(1/3) rho^(4/3)
     const F cs = F(0.7385587663820224);
@@ -134,6 +135,15 @@ __device__ __forceinline__ void b3lyp(F rho, F sigma, int vwn5, F& e, F& vr, F& 
     const F eB = F(-2) * rs43 * (Cx + beta * x * gx);
     const F vB = F(-4.0 / 3.0) * rs13 * (Cx + beta * x * (gx - x * gpx));
     const F sB = -beta * gpx / (F(4) * rs43);
+    e = F(0.08) * eS + F(0.72) * eB;
+    vr = F(0.08) * vS + F(0.72) * vB;
+    vs = F(0.72) * sB;
+}
+
+template <typename F>
+__device__ __forceinline__ void b3lyp_vwn(F rho, int vwn5, F& e, F& vr, F& vs)
+{
+    const F pi = F(kPi);
     // VWN (paramagnetic), x_v = sqrt(r_s)
     F b, c, x0;
     if (vwn5) { b = F(3.72744); c = F(12.9352); x0 = F(-0.10498); }
@@ -148,12 +158,18 @@ __device__ __forceinline__ void b3lyp(F rho, F sigma, int vwn5, F& e, F& vr, F& 
                          - bxX0 * (log((xv - x0) * (xv - x0) / X) + F(2) * (b + F(2) * x0) / Q * at));
     const F deps = Av * (F(2) / xv - (F(2) * xv + b) / X - b / X
                          - bxX0 * (F(2) / (xv - x0) - (F(2) * xv + b) / X - (b + F(2) * x0) / X));
-    const F eV = rho * epsv;
-    const F vV = epsv - xv * deps / F(6);
+    e = F(0.19) * rho * epsv;
+    vr = F(0.19) * (epsv - xv * deps / F(6));
+    vs = F(0);
+}
+
+template <typename F>
+__device__ __forceinline__ void b3lyp_lyp(F rho, F sigma, F& e, F& vr, F& vs)
+{
     // LYP, closed-shell gradient form; t = rho^(-1/3)
     const F la = F(0.04918), lb = F(0.132), lc = F(0.2533), ld = F(0.349);
     const F CF = F(2.8712340001881915);      // (3/10)(3 pi^2)^(2/3)
-    const F t = F(1) / r13, den = F(1) + ld * t, Ee = exp(-lc * t) / den;
+    const F t = F(1) / cbrt(rho), den = F(1) + ld * t, Ee = exp(-lc * t) / den;
     const F delta = lc * t + ld * t / den;
     const F t5 = t * t * t * t * t;          // rho^(-5/3)
     const F abE = la * lb * Ee;
@@ -162,9 +178,9 @@ __device__ __forceinline__ void b3lyp(F rho, F sigma, int vwn5, F& e, F& vr, F& 
                  + abE / F(72) * sigma * t5 / rho / F(3)
                        * (F(7) * delta * delta - F(39) * delta - F(15) + F(7) * ld * ld * t * t / (den * den));
     const F sL = abE / F(72) * t5 * (F(3) + F(7) * delta);
-    e = F(0.08) * eS + F(0.72) * eB + F(0.19) * eV + F(0.81) * eL;
-    vr = F(0.08) * vS + F(0.72) * vB + F(0.19) * vV + F(0.81) * vL;
-    vs = F(0.72) * sB + F(0.81) * sL;
+    e = F(0.81) * eL;
+    vr = F(0.81) * vL;
+    vs = F(0.81) * sL;
 }
 
 // ---------------------------------------------------------------------------
@@ -219,15 +235,27 @@ struct XcArgs {
     long part_stride;
     int vwn5;
     int only_active;
+    int ns_max;             // largest shell count of the batch (LDS shell table)
+};
+
+// Shell table of one molecule as the XC kernel keeps it in LDS: centres,
+// exponents and coefficients in the compute type, AO offset and L.
+template <typename T>
+struct ShellLds {
+    double* A;      // [ns][3]
+    T* ac;          // [ns][6]: a0 a1 a2 c0 c1 c2
+    int* info;      // [ns]: ao | L << 16
 };
 
 // Launch shapes.  BP points per sub-block, NW wavefronts per work group.
-// LDS: points, per-point coefficients, the padded density (the MFMA B
-// operand of X = Phi P, reused by every sub-block), Phi, grad Phi, X / W.
-__host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np)
+// LDS: points, the shell table, per-point density and gradient, the three
+// functional parts, the padded density (the MFMA B operand of X = Phi P,
+// reused by every sub-block), Phi, grad Phi, X / W.
+__host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np, int ns)
 {
-    return (size_t)bp * 4 * sizeof(double) + (size_t)nw * sizeof(double) + (size_t)bp * 4 * es
-           + (size_t)np * np * es + (size_t)5 * bp * (np + 1) * es + 64;
+    return (size_t)bp * 4 * sizeof(double) + (size_t)nw * sizeof(double) + (size_t)ns * 3 * sizeof(double)
+           + (size_t)ns * 6 * es + (size_t)bp * 4 * es + (size_t)bp * 9 * es + (size_t)np * np * es
+           + (size_t)5 * bp * (np + 1) * es + (size_t)ns * sizeof(int) + 64;
 }
 
 constexpr size_t kLdsMax = 163840;
@@ -300,30 +328,50 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
 {
     constexpr int NTH = NW * 64;
     constexpr int TPP = NTH / BP;     // threads per point in the density reduction
+    constexpr int PG = 64 / BP;       // point groups per wavefront (lane = point within a group)
+    constexpr int NG = NW * PG;       // point groups per work group
+    static_assert(NW >= 3, "the functional's three parts run on three wavefronts");
     typedef typename Mfma<T>::V V;
     const XcItem it = g.items[blockIdx.x];
     const int m = it.mol;
     if (g.only_active && g.state[m].status != KS_MOL_ACTIVE) return;
     const MolDesc md = g.mol[m];
     const int N = md.nbf, NP = md.np, NT = NP >> 4, LD = NP + 1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l16 = lane & 15;
+    const int gp = lane % BP, grp = wave * PG + lane / BP;   // point-per-lane view
     const int nj1 = ((BP / 16) * NT - wave + NW - 1) / NW;   // Phi P tiles of this wave
     const int nj2 = (NT * NT - wave + NW - 1) / NW;          // Phi^T W tiles of this wave
 
     extern __shared__ __align__(16) unsigned char smem_xc[];
     double* pts = (double*)smem_xc;                          // [BP][4]
     double* wsum = pts + BP * 4;                              // [NW]
-    T* coef = (T*)(wsum + NW);                                // [BP][4]
-    T* Pl = coef + BP * 4;                                    // [NP][NP]
+    ShellLds<T> shl;
+    shl.A = wsum + NW;                                        // [ns][3]
+    shl.ac = (T*)(shl.A + 3 * g.ns_max);                      // [ns][6]
+    T* coef = shl.ac + 6 * g.ns_max;                          // [BP][4]: rho, grad rho
+    T* fpart = coef + BP * 4;                                 // [3][BP][3]: e, v_rho, v_sigma per part
+    T* Pl = fpart + 9 * BP;                                   // [NP][NP]
     T* Phi = Pl + NP * NP;                                    // [BP][LD]
     T* dPhi = Phi + BP * LD;                                  // [3][BP][LD]
     T* XW = dPhi + 3 * BP * LD;                               // [BP][LD]
+    shl.info = (int*)(XW + BP * LD);                          // [ns]
 
     const T* __restrict__ Pt = (const T*)g.Pt + g.ptoff[m];
     const Shell* __restrict__ sh = g.shells + md.shell0;
 
     for (int i = tid; i < NP * NP; i += NTH) Pl[i] = Pt[i];
+    for (int i = tid; i < md.nshell; i += NTH) {
+        const Shell& S = sh[i];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            shl.A[3 * i + k] = S.A[k];
+            shl.ac[6 * i + k] = (T)S.a[k];
+            shl.ac[6 * i + 3 + k] = (T)S.c[k];
+        }
+        shl.info[i] = S.ao | (S.L << 16);
+    }
     for (int i = tid; i < 5 * BP * LD; i += NTH) Phi[i] = T(0);
 
     V acc[MAXT];
@@ -358,36 +406,44 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             }
         }
         __syncthreads();
-        // AO values and gradients: item = (point, shell), point fastest
-        for (int itx = tid; itx < BP * md.nshell; itx += NTH) {
-            const int gi = itx % BP, s = itx / BP;
-            const Shell S = sh[s];
-            const T dx = (T)(pts[4 * gi] - S.A[0]), dy = (T)(pts[4 * gi + 1] - S.A[1]), dz = (T)(pts[4 * gi + 2] - S.A[2]);
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            T R = T(0), dR = T(0);
+        // AO values and gradients: lane = point, each point group takes every
+        // NG-th shell (with one group per wavefront the shell is uniform)
+        {
+            const double px = pts[4 * gp], py = pts[4 * gp + 1], pz = pts[4 * gp + 2];
+            for (int s = grp; s < md.nshell; s += NG) {
+                const T dx = (T)(px - shl.A[3 * s]), dy = (T)(py - shl.A[3 * s + 1]), dz = (T)(pz - shl.A[3 * s + 2]);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T* ac = shl.ac + 6 * s;
+                T R = T(0), dR = T(0);
 #pragma unroll
-            for (int k = 0; k < kNPrim; k++) {
-                const T ar = (T)S.a[k] * r2;
-                if (ar < T(sizeof(T) == 4 ? 40 : 80)) {
-                    const T e = (T)S.c[k] * fast_exp(-ar);
-                    R += e;
-                    dR -= T(2) * (T)S.a[k] * e;
+                for (int k = 0; k < kNPrim; k++) {
+                    const T ar = ac[k] * r2;
+                    if constexpr (sizeof(T) == 4) {
+                        // the hardware exp2 flushes to 0 far below the FP32 range
+                        const T e = ac[3 + k] * fast_exp(-ar);
+                        R += e;
+                        dR -= T(2) * ac[k] * e;
+                    } else if (ar < T(80)) {
+                        const T e = ac[3 + k] * fast_exp(-ar);
+                        R += e;
+                        dR -= T(2) * ac[k] * e;
+                    }
                 }
-            }
-            const int mu = S.ao;
-            if (S.L == 0) {
-                Phi[gi * LD + mu] = R;
-                dPhi[gi * LD + mu] = dR * dx;
-                dPhi[(BP + gi) * LD + mu] = dR * dy;
-                dPhi[(2 * BP + gi) * LD + mu] = dR * dz;
-            } else {
-                const T d[3] = {dx, dy, dz};
+                const int info = shl.info[s], mu = info & 0xffff;
+                if ((info >> 16) == 0) {
+                    Phi[gp * LD + mu] = R;
+                    dPhi[gp * LD + mu] = dR * dx;
+                    dPhi[(BP + gp) * LD + mu] = dR * dy;
+                    dPhi[(2 * BP + gp) * LD + mu] = dR * dz;
+                } else {
+                    const T d[3] = {dx, dy, dz};
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    Phi[gi * LD + mu + c] = d[c] * R;
+                    for (int c = 0; c < 3; c++) {
+                        Phi[gp * LD + mu + c] = d[c] * R;
 #pragma unroll
-                    for (int k = 0; k < 3; k++)
-                        dPhi[(k * BP + gi) * LD + mu + c] = (k == c ? R : T(0)) + d[c] * d[k] * dR;
+                        for (int k = 0; k < 3; k++)
+                            dPhi[(k * BP + gp) * LD + mu + c] = (k == c ? R : T(0)) + d[c] * d[k] * dR;
+                    }
                 }
             }
         }
@@ -430,32 +486,42 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             }
         }
         __syncthreads();
-        // functional: one wave, one point per lane (every other wave would
-        // repeat the same instruction stream with most lanes idle)
-        if (wave == 0 && lane < BP) {
+        // functional: wavefronts 0, 1, 2 evaluate the exchange, VWN and LYP
+        // parts for every point of the sub-block (lane = point)
+        if (wave < 3 && lane < BP) {
             const int gi = lane;
             const T r = coef[4 * gi], gx = coef[4 * gi + 1], gy = coef[4 * gi + 2], gz = coef[4 * gi + 3];
             const T w = (T)pts[4 * gi + 3];
-            T c0 = T(0), c1 = T(0), c2 = T(0), c3 = T(0);
+            T e = T(0), vr = T(0), vs = T(0);
             if (r >= T(kRhoCut) && w != T(0)) {
-                T e, vr, vs;
-                b3lyp<T>(r, gx * gx + gy * gy + gz * gz, g.vwn5, e, vr, vs);
+                const T sg = gx * gx + gy * gy + gz * gz;
+                if (wave == 0) b3lyp_exchange<T>(r, sg, e, vr, vs);
+                else if (wave == 1) b3lyp_vwn<T>(r, g.vwn5, e, vr, vs);
+                else b3lyp_lyp<T>(r, sg, e, vr, vs);
                 const double we = (double)w * (double)e;
                 const double tt = exc + we;
                 if (fabs(exc) >= fabs(we)) exc_c += (exc - tt) + we; else exc_c += (we - tt) + exc;
                 exc = tt;
-                c0 = T(0.5) * w * vr;
-                const T s2 = T(2) * w * vs;
-                c1 = s2 * gx; c2 = s2 * gy; c3 = s2 * gz;
             }
-            coef[4 * gi] = c0; coef[4 * gi + 1] = c1; coef[4 * gi + 2] = c2; coef[4 * gi + 3] = c3;
+            T* fp = fpart + (wave * BP + gi) * 3;
+            fp[0] = e; fp[1] = vr; fp[2] = vs;
         }
         __syncthreads();
-        // W = c0 Phi + c . grad Phi   (overwrites X)
-        for (int idx = tid; idx < BP * NP; idx += NTH) {
-            const int gi = idx / NP, mu = idx % NP;
-            XW[gi * LD + mu] = coef[4 * gi] * Phi[gi * LD + mu] + coef[4 * gi + 1] * dPhi[gi * LD + mu]
-                             + coef[4 * gi + 2] * dPhi[(BP + gi) * LD + mu] + coef[4 * gi + 3] * dPhi[(2 * BP + gi) * LD + mu];
+        // W = c0 Phi + c . grad Phi (overwrites X), c0 = w v_rho / 2,
+        // c = 2 w v_sigma grad rho; lane = point, each point group a column range
+        {
+            const T w = (T)pts[4 * gp + 3];
+            const T vr = fpart[gp * 3 + 1] + fpart[(BP + gp) * 3 + 1] + fpart[(2 * BP + gp) * 3 + 1];
+            const T vs = fpart[gp * 3 + 2] + fpart[(BP + gp) * 3 + 2] + fpart[(2 * BP + gp) * 3 + 2];
+            const T c0 = T(0.5) * w * vr, s2 = T(2) * w * vs;
+            const T c1 = s2 * coef[4 * gp + 1], c2 = s2 * coef[4 * gp + 2], c3 = s2 * coef[4 * gp + 3];
+            const int cw = (NP + NG - 1) / NG, m0 = grp * cw, m1 = min(NP, m0 + cw);
+            const T* ph = Phi + gp * LD;
+            const T* d0 = dPhi + gp * LD;
+            const T* d1 = dPhi + (BP + gp) * LD;
+            const T* d2 = dPhi + (2 * BP + gp) * LD;
+            T* xw = XW + gp * LD;
+            for (int mu = m0; mu < m1; mu++) xw[mu] = c0 * ph[mu] + c1 * d0[mu] + c2 * d1[mu] + c3 * d2[mu];
         }
         __syncthreads();
         // A += Phi^T W   (NP x BP) . (BP x NP), this wave's tiles
@@ -549,8 +615,8 @@ XcShape xc_shape(const ks_batch* b)
         const int nw = b->opt.xc_waves > 0 ? b->opt.xc_waves : s.nw;
         if (xc_shape_ok(bp, nw)) { s.bp = bp; s.nw = nw; }
     }
-    while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np) > kLdsMax) s.bp /= 2;
-    s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np);
+    while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell) > kLdsMax) s.bp /= 2;
+    s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell);
     return s;
 }
 
@@ -590,6 +656,7 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
     g.part = b->d_xc_part;
     g.part_exc = b->d_xc_exc;
     g.part_stride = (long)b->max_np * b->max_np;
+    g.ns_max = b->max_nshell;
     g.vwn5 = b->opt.xc == KS_XC_B3LYP5;
     g.only_active = only_active;
     const XcShape s = xc_shape(b);

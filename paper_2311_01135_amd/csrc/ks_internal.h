@@ -111,6 +111,7 @@ struct ks_batch {
     hipStream_t stream = nullptr;
     int n_mol = 0;
     int max_np = 0;
+    int max_nshell = 0;
     double a0 = 0.2;
     std::vector<ks::MolDesc> mol;
     std::vector<ks::Shell> shells;
