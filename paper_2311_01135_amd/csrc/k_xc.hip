@@ -7,13 +7,16 @@
 // in cos(theta) x trapezoid in phi, weighted by Becke fuzzy-cell functions
 // (three smoothing steps, no size adjustment).
 //
-// XC: one work group (8 wavefronts) walks a contiguous chunk of one
-// molecule's grid in sub-blocks of BP points.  Per sub-block it evaluates the
-// AO values and gradients into LDS, forms X = Phi P with 16x16x4 MFMAs (P read
-// from L2), reduces rho = sum X Phi and grad rho = 2 sum X grad Phi per point,
-// evaluates B3LYP, forms W = w (v_rho/2 Phi + 2 v_sigma grad rho . grad Phi),
-// and accumulates A += Phi^T W with MFMAs into register tiles that persist over
-// the whole chunk.  V_XC = sum_chunks (A + A^T) is summed in FP64 afterwards.
+// XC: one work group walks a contiguous chunk of one molecule's grid in
+// sub-blocks of BP points, with the molecule's density P and shell table in
+// LDS.  Per sub-block it evaluates the AO values and gradients into AO-major
+// LDS planes, forms X^T = P Phi^T with 16x16x4 MFMAs and, from each X tile
+// still in registers, its share of rho = sum X Phi and grad rho =
+// 2 sum X grad Phi; evaluates B3LYP (three wavefronts, one part each); forms
+// W = w (v_rho/2 Phi + 2 v_sigma grad rho . grad Phi) in place of d/dx Phi;
+// and accumulates A += Phi^T W with MFMAs into register tiles that persist
+// over the whole chunk.  V_XC = sum_chunks (A + A^T) is summed in FP64
+// afterwards.
 #include "kernels.h"
 
 namespace ks {
@@ -248,77 +251,123 @@ struct ShellLds {
 };
 
 // Launch shapes.  BP points per sub-block, NW wavefronts per work group.
-// LDS: points, the shell table, per-point density and gradient, the three
-// functional parts, the padded density (the MFMA B operand of X = Phi P,
-// reused by every sub-block), Phi, grad Phi, X / W.
+// LDS, each piece 32-byte aligned: points and per-wave sums (FP64), the
+// shell table, per-point density and gradient, the three functional parts,
+// the per-AO-tile density partials, the padded density P (row stride NP + 4)
+// and four AO-major planes [AO][point] (row stride BP + 4): Phi, d/dx Phi
+// (overwritten by W once the density is formed), d/dy Phi, d/dz Phi.
+__host__ __device__ constexpr size_t al32(size_t x) { return (x + 31) & ~(size_t)31; }
+__host__ __device__ constexpr int xc_ldp(int np) { return np + 4; }
+__host__ __device__ constexpr int xc_ldg(int bp) { return bp + 4; }
 __host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np, int ns)
 {
-    return (size_t)bp * 4 * sizeof(double) + (size_t)nw * sizeof(double) + (size_t)ns * 3 * sizeof(double)
-           + (size_t)ns * 6 * es + (size_t)bp * 4 * es + (size_t)bp * 9 * es + (size_t)np * np * es
-           + (size_t)5 * bp * (np + 1) * es + (size_t)ns * sizeof(int) + 64;
+    return al32((size_t)bp * 4 * sizeof(double)) + al32((size_t)nw * sizeof(double))
+           + al32((size_t)ns * 3 * sizeof(double)) + al32((size_t)ns * 6 * es) + al32((size_t)bp * 4 * es)
+           + al32((size_t)bp * 9 * es) + al32((size_t)(np / 16) * 4 * bp * es) + al32((size_t)np * xc_ldp(np) * es)
+           + al32((size_t)4 * np * xc_ldg(bp) * es) + al32((size_t)ns * sizeof(int));
 }
 
 constexpr size_t kLdsMax = 163840;
 
-// X tiles (t = wave + NW j, j < NJ) of X = Phi P: NJ independent MFMA chains,
-// K = NP (a multiple of 16) unrolled by 16; no branches inside the loop.
-template <typename T, int NW, int NJ>
-__device__ __forceinline__ void gemm_phi_p(const T* __restrict__ Phi, const T* __restrict__ Pl, T* __restrict__ XW,
-                                           int LD, int NP, int NT, int wave, int lane)
+// The MFMA k index runs over 16-wide blocks: within a block, lane group
+// q = lane / 16 supplies k = 4 q + j to the j-th of four MFMAs, so a lane's
+// four values along k are contiguous in LDS (one vector read) whenever the
+// operand is stored k-contiguous.
+
+// X^T tiles (t = wave + NW j, j < NJ; AO tile t / (BP/16), point tile
+// t % (BP/16)) of X^T = P Phi^T over K = NP, then, from the tile in
+// registers, this tile's share of rho = sum_mu X Phi and of
+// sum_mu X grad Phi at its 16 points, written to rpart[AO tile][4][BP].
+template <typename T, int BP, int NW, int NJ>
+__device__ __forceinline__ void gemm_x_rho(const T* __restrict__ Pl, const T* __restrict__ Phi, T* __restrict__ rpart,
+                                           int LDP, int LDG, int PL, int NP, int wave, int lane)
 {
     typedef typename Mfma<T>::V V;
-    const int l16 = lane & 15, l4 = lane >> 4;
+    constexpr int GT = BP / 16;
+    const int l16 = lane & 15, q = lane >> 4;
     V c[NJ];
-    int ra[NJ], cb[NJ];
+    int pa[NJ], pb[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
         const int t = wave + j * NW;
-        ra[j] = (t / NT) * 16 + l16;
-        cb[j] = (t % NT) * 16 + l16;
+        pa[j] = ((t / GT) * 16 + l16) * LDP + 4 * q;
+        pb[j] = 4 * q * LDG + (t % GT) * 16 + l16;
 #pragma unroll
         for (int r = 0; r < 4; r++) c[j][r] = T(0);
     }
     for (int kk = 0; kk < NP; kk += 16) {
+        V a[NJ];
+        T bv[NJ][4];
 #pragma unroll
-        for (int k4 = 0; k4 < 16; k4 += 4) {
+        for (int j = 0; j < NJ; j++) {
+            a[j] = *(const V*)(Pl + pa[j] + kk);
+            const T* pbk = Phi + pb[j] + kk * LDG;
 #pragma unroll
-            for (int j = 0; j < NJ; j++) {
-                const T a = Phi[ra[j] * LD + kk + k4 + l4];
-                const T b = Pl[(kk + k4 + l4) * NP + cb[j]];
-                c[j] = Mfma<T>::run(a, b, c[j]);
-            }
+            for (int i = 0; i < 4; i++) bv[j][i] = pbk[i * LDG];
         }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < NJ; j++) c[j] = Mfma<T>::run(a[j][i], bv[j][i], c[j]);
     }
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
-        const int r0 = ((wave + j * NW) / NT) * 16;
+        const int t = wave + j * NW, mt = t / GT, gpt = (t % GT) * 16 + l16;
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll
-        for (int r = 0; r < 4; r++) XW[(r0 + Mfma<T>::row(lane, r)) * LD + cb[j]] = c[j][r];
+        for (int r = 0; r < 4; r++) {
+            const int o = (mt * 16 + Mfma<T>::row(lane, r)) * LDG + gpt;
+            const T x = c[j][r];
+            s0 += x * Phi[o];
+            s1 += x * Phi[PL + o];
+            s2 += x * Phi[2 * PL + o];
+            s3 += x * Phi[3 * PL + o];
+        }
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            s0 += __shfl_xor(s0, o, 64);
+            s1 += __shfl_xor(s1, o, 64);
+            s2 += __shfl_xor(s2, o, 64);
+            s3 += __shfl_xor(s3, o, 64);
+        }
+        if (q == 0) {
+            T* rp = rpart + mt * 4 * BP + gpt;
+            rp[0] = s0;
+            rp[BP] = s1;
+            rp[2 * BP] = s2;
+            rp[3 * BP] = s3;
+        }
     }
 }
 
-// acc[j] += tile (t = wave + NW j) of Phi^T W over the BP points of a sub-block.
+// acc[j] += tile (t = wave + NW j) of Phi^T W over the BP points of a
+// sub-block; both operands AO-major, so each k block is two vector reads.
 template <typename T, int NW, int BP, int MAXT, int NJ>
-__device__ __forceinline__ void gemm_phit_w(const T* __restrict__ Phi, const T* __restrict__ XW, int LD, int NT,
+__device__ __forceinline__ void gemm_phit_w(const T* __restrict__ Phi, const T* __restrict__ Wt, int LDG, int NT,
                                             int wave, int lane, typename Mfma<T>::V (&acc)[MAXT])
 {
     if constexpr (NJ <= MAXT) {
-        const int l16 = lane & 15, l4 = lane >> 4;
-        int ca[NJ], cb[NJ];
+        typedef typename Mfma<T>::V V;
+        const int l16 = lane & 15, q = lane >> 4;
+        int pa[NJ], pb[NJ];
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
             const int t = wave + j * NW;
-            ca[j] = (t / NT) * 16 + l16;
-            cb[j] = (t % NT) * 16 + l16;
+            pa[j] = ((t / NT) * 16 + l16) * LDG + 4 * q;
+            pb[j] = ((t % NT) * 16 + l16) * LDG + 4 * q;
         }
-#pragma unroll 2
-        for (int kk = 0; kk < BP; kk += 4) {
+#pragma unroll
+        for (int kk = 0; kk < BP; kk += 16) {
+            V a[NJ], bv[NJ];
 #pragma unroll
             for (int j = 0; j < NJ; j++) {
-                const T a = Phi[(kk + l4) * LD + ca[j]];
-                const T b = XW[(kk + l4) * LD + cb[j]];
-                acc[j] = Mfma<T>::run(a, b, acc[j]);
+                a[j] = *(const V*)(Phi + pa[j] + kk);
+                bv[j] = *(const V*)(Wt + pb[j] + kk);
             }
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < NJ; j++) acc[j] = Mfma<T>::run(a[j][i], bv[j][i], acc[j]);
         }
     }
 }
@@ -327,41 +376,48 @@ template <typename T, int BP, int NW, int MAXT>
 __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
 {
     constexpr int NTH = NW * 64;
-    constexpr int TPP = NTH / BP;     // threads per point in the density reduction
     constexpr int PG = 64 / BP;       // point groups per wavefront (lane = point within a group)
     constexpr int NG = NW * PG;       // point groups per work group
+    constexpr int GT = BP / 16;       // point tiles
+    constexpr int LDG = xc_ldg(BP);
     static_assert(NW >= 3, "the functional's three parts run on three wavefronts");
     typedef typename Mfma<T>::V V;
     const XcItem it = g.items[blockIdx.x];
     const int m = it.mol;
     if (g.only_active && g.state[m].status != KS_MOL_ACTIVE) return;
     const MolDesc md = g.mol[m];
-    const int N = md.nbf, NP = md.np, NT = NP >> 4, LD = NP + 1;
+    const int N = md.nbf, NP = md.np, NT = NP >> 4, LDP = xc_ldp(NP), PL = NP * LDG;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l16 = lane & 15;
     const int gp = lane % BP, grp = wave * PG + lane / BP;   // point-per-lane view
-    const int nj1 = ((BP / 16) * NT - wave + NW - 1) / NW;   // Phi P tiles of this wave
+    const int nj1 = (GT * NT - wave + NW - 1) / NW;          // X^T tiles of this wave
     const int nj2 = (NT * NT - wave + NW - 1) / NW;          // Phi^T W tiles of this wave
 
-    extern __shared__ __align__(16) unsigned char smem_xc[];
-    double* pts = (double*)smem_xc;                          // [BP][4]
-    double* wsum = pts + BP * 4;                              // [NW]
+    extern __shared__ __align__(32) unsigned char smem_xc[];
+    unsigned char* cur = smem_xc;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = cur;
+        cur += al32(bytes);
+        return p;
+    };
+    double* pts = (double*)take(BP * 4 * sizeof(double));    // [BP][4]
+    double* wsum = (double*)take(NW * sizeof(double));        // [NW]
     ShellLds<T> shl;
-    shl.A = wsum + NW;                                        // [ns][3]
-    shl.ac = (T*)(shl.A + 3 * g.ns_max);                      // [ns][6]
-    T* coef = shl.ac + 6 * g.ns_max;                          // [BP][4]: rho, grad rho
-    T* fpart = coef + BP * 4;                                 // [3][BP][3]: e, v_rho, v_sigma per part
-    T* Pl = fpart + 9 * BP;                                   // [NP][NP]
-    T* Phi = Pl + NP * NP;                                    // [BP][LD]
-    T* dPhi = Phi + BP * LD;                                  // [3][BP][LD]
-    T* XW = dPhi + 3 * BP * LD;                               // [BP][LD]
-    shl.info = (int*)(XW + BP * LD);                          // [ns]
+    shl.A = (double*)take((size_t)g.ns_max * 3 * sizeof(double));
+    shl.ac = (T*)take((size_t)g.ns_max * 6 * sizeof(T));
+    T* coef = (T*)take(BP * 4 * sizeof(T));                   // [BP][4]: rho, grad rho
+    T* fpart = (T*)take(BP * 9 * sizeof(T));                  // [3][BP][3]: e, v_rho, v_sigma per part
+    T* rpart = (T*)take((size_t)NT * 4 * BP * sizeof(T));     // [NT][4][BP]
+    T* Pl = (T*)take((size_t)NP * LDP * sizeof(T));           // [NP][LDP]
+    T* Phi = (T*)take((size_t)4 * PL * sizeof(T));            // 4 planes [NP][LDG]
+    T* Wt = Phi + PL;                                         // W^T overwrites d/dx Phi
+    shl.info = (int*)take((size_t)g.ns_max * sizeof(int));
 
     const T* __restrict__ Pt = (const T*)g.Pt + g.ptoff[m];
     const Shell* __restrict__ sh = g.shells + md.shell0;
 
-    for (int i = tid; i < NP * NP; i += NTH) Pl[i] = Pt[i];
+    for (int i = tid; i < NP * NP; i += NTH) Pl[(i / NP) * LDP + i % NP] = Pt[i];
     for (int i = tid; i < md.nshell; i += NTH) {
         const Shell& S = sh[i];
 #pragma unroll
@@ -372,7 +428,7 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
         }
         shl.info[i] = S.ao | (S.L << 16);
     }
-    for (int i = tid; i < 5 * BP * LD; i += NTH) Phi[i] = T(0);
+    for (int i = tid; i < 4 * PL; i += NTH) Phi[i] = T(0);
 
     V acc[MAXT];
 #pragma unroll
@@ -397,17 +453,18 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             pts[4 * tid + 2] = nxt[2];
             pts[4 * tid + 3] = nxt[3];
             // issue the next sub-block's loads; they complete behind this one
-            const long gp = g0 + BP + tid;
-            if (gp < it.g1) {
-                const double* src = g.grid + 4 * (md.grid0 + gp);
+            const long gn = g0 + BP + tid;
+            if (gn < it.g1) {
+                const double* src = g.grid + 4 * (md.grid0 + gn);
                 nxt[0] = src[0]; nxt[1] = src[1]; nxt[2] = src[2]; nxt[3] = src[3];
             } else {
                 nxt[0] = far[0]; nxt[1] = far[1]; nxt[2] = far[2]; nxt[3] = 0.0;
             }
         }
         __syncthreads();
-        // AO values and gradients: lane = point, each point group takes every
-        // NG-th shell (with one group per wavefront the shell is uniform)
+        // AO values and gradients into the AO-major planes: lane = point,
+        // each point group takes every NG-th shell (with one group per
+        // wavefront the shell is uniform)
         {
             const double px = pts[4 * gp], py = pts[4 * gp + 1], pz = pts[4 * gp + 2];
             for (int s = grp; s < md.nshell; s += NG) {
@@ -430,67 +487,58 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
                     }
                 }
                 const int info = shl.info[s], mu = info & 0xffff;
+                T* o = Phi + mu * LDG + gp;
                 if ((info >> 16) == 0) {
-                    Phi[gp * LD + mu] = R;
-                    dPhi[gp * LD + mu] = dR * dx;
-                    dPhi[(BP + gp) * LD + mu] = dR * dy;
-                    dPhi[(2 * BP + gp) * LD + mu] = dR * dz;
+                    o[0] = R;
+                    o[PL] = dR * dx;
+                    o[2 * PL] = dR * dy;
+                    o[3 * PL] = dR * dz;
                 } else {
                     const T d[3] = {dx, dy, dz};
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        Phi[gp * LD + mu + c] = d[c] * R;
+                        o[c * LDG] = d[c] * R;
 #pragma unroll
                         for (int k = 0; k < 3; k++)
-                            dPhi[(k * BP + gp) * LD + mu + c] = (k == c ? R : T(0)) + d[c] * d[k] * dR;
+                            o[(k + 1) * PL + c * LDG] = (k == c ? R : T(0)) + d[c] * d[k] * dR;
                     }
                 }
             }
         }
         __syncthreads();
-        // X = Phi P   (BP x NP) . (NP x NP): this wave's tiles, dispatched once
-        // to a branch-free body with a compile-time tile count
+        // X^T = P Phi^T and the density partials, this wave's tiles,
+        // dispatched once to a branch-free body with a compile-time tile
+        // count.  The lane index passes through an empty asm so that the tile
+        // addresses are formed here, per sub-block, instead of being hoisted
+        // out of the loop for every case (which exhausts the registers).
+        int lane_g = lane;
+        asm volatile("" : "+v"(lane_g));
         switch (nj1) {
-        case 1: gemm_phi_p<T, NW, 1>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
-        case 2: gemm_phi_p<T, NW, 2>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
-        case 3: gemm_phi_p<T, NW, 3>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
-        case 4: gemm_phi_p<T, NW, 4>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
-        case 5: gemm_phi_p<T, NW, 5>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
-        case 6: gemm_phi_p<T, NW, 6>(Phi, Pl, XW, LD, NP, NT, wave, lane); break;
+        case 1: gemm_x_rho<T, BP, NW, 1>(Pl, Phi, rpart, LDP, LDG, PL, NP, wave, lane_g); break;
+        case 2: gemm_x_rho<T, BP, NW, 2>(Pl, Phi, rpart, LDP, LDG, PL, NP, wave, lane_g); break;
+        case 3: gemm_x_rho<T, BP, NW, 3>(Pl, Phi, rpart, LDP, LDG, PL, NP, wave, lane_g); break;
+        case 4: gemm_x_rho<T, BP, NW, 4>(Pl, Phi, rpart, LDP, LDG, PL, NP, wave, lane_g); break;
+        case 5: gemm_x_rho<T, BP, NW, 5>(Pl, Phi, rpart, LDP, LDG, PL, NP, wave, lane_g); break;
+        case 6: gemm_x_rho<T, BP, NW, 6>(Pl, Phi, rpart, LDP, LDG, PL, NP, wave, lane_g); break;
         default: break;
-        }
-        __syncthreads();
-        // rho and grad rho per point (TPP lanes per point), staged in coef
-        {
-            const int gi = tid / TPP, sub = tid % TPP;
-            T r = T(0), gx = T(0), gy = T(0), gz = T(0);
-            for (int mu = sub; mu < N; mu += TPP) {
-                const T xv = XW[gi * LD + mu];
-                r += xv * Phi[gi * LD + mu];
-                gx += xv * dPhi[gi * LD + mu];
-                gy += xv * dPhi[(BP + gi) * LD + mu];
-                gz += xv * dPhi[(2 * BP + gi) * LD + mu];
-            }
-#pragma unroll
-            for (int o = TPP / 2; o >= 1; o >>= 1) {
-                r += __shfl_xor(r, o, TPP);
-                gx += __shfl_xor(gx, o, TPP);
-                gy += __shfl_xor(gy, o, TPP);
-                gz += __shfl_xor(gz, o, TPP);
-            }
-            if (sub == 0) {
-                coef[4 * gi] = r;
-                coef[4 * gi + 1] = T(2) * gx;
-                coef[4 * gi + 2] = T(2) * gy;
-                coef[4 * gi + 3] = T(2) * gz;
-            }
         }
         __syncthreads();
         // functional: wavefronts 0, 1, 2 evaluate the exchange, VWN and LYP
         // parts for every point of the sub-block (lane = point)
         if (wave < 3 && lane < BP) {
             const int gi = lane;
-            const T r = coef[4 * gi], gx = coef[4 * gi + 1], gy = coef[4 * gi + 2], gz = coef[4 * gi + 3];
+            T r = T(0), gx = T(0), gy = T(0), gz = T(0);
+            for (int mt = 0; mt < NT; mt++) {
+                const T* rp = rpart + mt * 4 * BP + gi;
+                r += rp[0];
+                gx += rp[BP];
+                gy += rp[2 * BP];
+                gz += rp[3 * BP];
+            }
+            gx *= T(2); gy *= T(2); gz *= T(2);
+            if (wave == 0) {
+                coef[4 * gi] = r; coef[4 * gi + 1] = gx; coef[4 * gi + 2] = gy; coef[4 * gi + 3] = gz;
+            }
             const T w = (T)pts[4 * gi + 3];
             T e = T(0), vr = T(0), vs = T(0);
             if (r >= T(kRhoCut) && w != T(0)) {
@@ -507,8 +555,8 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             fp[0] = e; fp[1] = vr; fp[2] = vs;
         }
         __syncthreads();
-        // W = c0 Phi + c . grad Phi (overwrites X), c0 = w v_rho / 2,
-        // c = 2 w v_sigma grad rho; lane = point, each point group a column range
+        // W^T = c0 Phi + c . grad Phi in place of d/dx Phi, c0 = w v_rho / 2,
+        // c = 2 w v_sigma grad rho; lane = point, each point group an AO range
         {
             const T w = (T)pts[4 * gp + 3];
             const T vr = fpart[gp * 3 + 1] + fpart[(BP + gp) * 3 + 1] + fpart[(2 * BP + gp) * 3 + 1];
@@ -516,25 +564,25 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             const T c0 = T(0.5) * w * vr, s2 = T(2) * w * vs;
             const T c1 = s2 * coef[4 * gp + 1], c2 = s2 * coef[4 * gp + 2], c3 = s2 * coef[4 * gp + 3];
             const int cw = (NP + NG - 1) / NG, m0 = grp * cw, m1 = min(NP, m0 + cw);
-            const T* ph = Phi + gp * LD;
-            const T* d0 = dPhi + gp * LD;
-            const T* d1 = dPhi + (BP + gp) * LD;
-            const T* d2 = dPhi + (2 * BP + gp) * LD;
-            T* xw = XW + gp * LD;
-            for (int mu = m0; mu < m1; mu++) xw[mu] = c0 * ph[mu] + c1 * d0[mu] + c2 * d1[mu] + c3 * d2[mu];
+            for (int mu = m0; mu < m1; mu++) {
+                T* o = Phi + mu * LDG + gp;
+                o[PL] = c0 * o[0] + c1 * o[PL] + c2 * o[2 * PL] + c3 * o[3 * PL];
+            }
         }
         __syncthreads();
         // A += Phi^T W   (NP x BP) . (BP x NP), this wave's tiles
+        lane_g = lane;
+        asm volatile("" : "+v"(lane_g));
         switch (nj2) {
-        case 1: gemm_phit_w<T, NW, BP, MAXT, 1>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 2: gemm_phit_w<T, NW, BP, MAXT, 2>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 3: gemm_phit_w<T, NW, BP, MAXT, 3>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 4: gemm_phit_w<T, NW, BP, MAXT, 4>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 5: gemm_phit_w<T, NW, BP, MAXT, 5>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 6: gemm_phit_w<T, NW, BP, MAXT, 6>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 7: gemm_phit_w<T, NW, BP, MAXT, 7>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 8: gemm_phit_w<T, NW, BP, MAXT, 8>(Phi, XW, LD, NT, wave, lane, acc); break;
-        case 9: gemm_phit_w<T, NW, BP, MAXT, 9>(Phi, XW, LD, NT, wave, lane, acc); break;
+        case 1: gemm_phit_w<T, NW, BP, MAXT, 1>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 2: gemm_phit_w<T, NW, BP, MAXT, 2>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 3: gemm_phit_w<T, NW, BP, MAXT, 3>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 4: gemm_phit_w<T, NW, BP, MAXT, 4>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 5: gemm_phit_w<T, NW, BP, MAXT, 5>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 6: gemm_phit_w<T, NW, BP, MAXT, 6>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 7: gemm_phit_w<T, NW, BP, MAXT, 7>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 8: gemm_phit_w<T, NW, BP, MAXT, 8>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
+        case 9: gemm_phit_w<T, NW, BP, MAXT, 9>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
         default: break;
         }
     }
@@ -600,7 +648,7 @@ __global__ void xc_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
 // LDS budget (160 KB) holds.
 static bool xc_shape_ok(int bp, int nw)
 {
-    return (bp == 16 || bp == 32 || bp == 64) && (nw == 4 || nw == 8);
+    return (bp == 16 || bp == 32 || bp == 64) && (nw == 4 || nw == 8 || nw == 16);
 }
 
 XcShape xc_shape(const ks_batch* b)
@@ -662,7 +710,11 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
     const XcShape s = xc_shape(b);
     const bool big = b->max_np > 80;     // 6 x 6 tiles of 16
     ks_status st;
-    if (s.nw == 8) {
+    if (s.nw == 16) {
+        if (s.bp == 64) st = big ? launch_xc_shape<T, 64, 16, 3>(b, g, s.lds) : launch_xc_shape<T, 64, 16, 2>(b, g, s.lds);
+        else if (s.bp == 32) st = big ? launch_xc_shape<T, 32, 16, 3>(b, g, s.lds) : launch_xc_shape<T, 32, 16, 2>(b, g, s.lds);
+        else st = big ? launch_xc_shape<T, 16, 16, 3>(b, g, s.lds) : launch_xc_shape<T, 16, 16, 2>(b, g, s.lds);
+    } else if (s.nw == 8) {
         if (s.bp == 64) st = big ? launch_xc_shape<T, 64, 8, 5>(b, g, s.lds) : launch_xc_shape<T, 64, 8, 4>(b, g, s.lds);
         else if (s.bp == 32) st = big ? launch_xc_shape<T, 32, 8, 5>(b, g, s.lds) : launch_xc_shape<T, 32, 8, 4>(b, g, s.lds);
         else st = big ? launch_xc_shape<T, 16, 8, 5>(b, g, s.lds) : launch_xc_shape<T, 16, 8, 4>(b, g, s.lds);
