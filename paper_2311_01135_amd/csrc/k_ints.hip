@@ -144,7 +144,8 @@ struct PairView {
 // ---------------------------------------------------------------------------
 template <int LA, int LB, int LC, int LD, typename R>
 __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, const Shell& sc, const Shell& sd,
-                                            const PairView& vb, const PairView& vk, const R* __restrict__ tab, R* acc)
+                                            const PairView& vb, const PairView& vk, const R* __restrict__ tab, R cut,
+                                            R* acc)
 {
     constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
@@ -154,7 +155,8 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
     for (int ip = 0; ip < kNPrimPair; ip++) {
         const double bP[3] = {vb.get(1, ip), vb.get(2, ip), vb.get(3, ip)};
         const R p = R(vb.get(0, ip)), Kb = R(vb.get(4, ip));
-        if (Kb == R(0)) continue;
+        // negligible for every ket: q >= kQMin and |K_cd| <= kKMax bound the prefactor
+        if (fabs(Kb) * pi25 * R(kKMax) / (p * R(kQMin) * sqrt(p + R(kQMin))) < cut) continue;
         R eb[3][4][3];
         const R i2p = R(0.5) / p;
 #pragma unroll
@@ -162,7 +164,8 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
         for (int jp = 0; jp < kNPrimPair; jp++) {
             const double kP[3] = {vk.get(1, jp), vk.get(2, jp), vk.get(3, jp)};
             const R q = R(vk.get(0, jp)), Kk = R(vk.get(4, jp));
-            if (Kk == R(0)) continue;
+            const R pref = pi25 / (p * q * sqrt(p + q)) * Kb * Kk;
+            if (fabs(pref) < cut) continue;
             R ek[3][4][3];
             const R i2q = R(0.5) / q;
 #pragma unroll
@@ -174,7 +177,6 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
             boys<L, R>(T, F, tab);
             R Rt[L + 1][L + 1][L + 1];
             hermite_R<L, R>(R(-2) * alpha, PQx, PQy, PQz, F, Rt);
-            const R pref = pi25 / (p * q * sqrt(pq)) * Kb * Kk;
 #pragma unroll
             for (int kc = 0; kc < NC; kc++)
 #pragma unroll
@@ -278,6 +280,7 @@ struct EriArgs {
     long npb, npk;
     const void* tab;
     void* out;              // [ncomp][nq]
+    double cut;             // primitive quartets with |prefactor| below this are skipped
 };
 
 template <int LA, int LB, int LC, int LD, typename R, typename S>
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(128) void eri_class_kernel(EriArgs g)
     const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
     R acc[NCOMP];
     const PairView vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
-    eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, (const R*)g.tab, acc);
+    eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, (const R*)g.tab, R(g.cut), acc);
     S* out = (S*)g.out;
 #pragma unroll
     for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
@@ -485,6 +488,7 @@ static ks_status launch_class(ks_batch* b, int c)
     g.npb = b->npairs[class_bra(c)];
     g.npk = b->npairs[class_ket(c)];
     g.tab = std::is_same<R, double>::value ? (const void*)b->d_boys : (const void*)b->d_boys_f;
+    g.cut = b->opt.prec == KS_MIXED ? kEriCutMixed : kEriCutFp64;
     g.out = b->d_eri[c];
     const long nb = (g.nq + 127) / 128;
     hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S>), dim3((unsigned)nb), dim3(128), 0, b->stream, g);

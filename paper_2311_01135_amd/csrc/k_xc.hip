@@ -24,27 +24,35 @@ namespace ks {
 // ---------------------------------------------------------------------------
 // grid points and Becke weights
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double becke_s(double mu)
+// Becke's smoothing polynomial applied three times, f3(mu); the cell
+// function is s(mu) = (1 - f3(mu))/2, and f3 is odd, so s(-mu) = (1 + f3(mu))/2.
+__device__ __forceinline__ double becke_f3(double mu)
 {
 #pragma unroll
     for (int k = 0; k < 3; k++) mu = 1.5 * mu - 0.5 * mu * mu * mu;
-    return 0.5 * (1.0 - mu);
+    return mu;
 }
 
-// blockIdx.y = molecule; each thread one of its points.  LDS: atom positions
-// and per-thread distances to every atom (transposed: [atom][thread]).
-__global__ __launch_bounds__(128) void grid_kernel(const MolDesc* __restrict__ mols, const double* __restrict__ Rat,
-                                                   const double* __restrict__ radial, const double* __restrict__ ang,
-                                                   int nrad, int nth, int nph, double* __restrict__ out)
+// blockIdx.y = molecule; each thread one of its points.  LDS: atom
+// positions, inverse interatomic distances, and per thread the distances to
+// every atom and the cell products P_a (both transposed: [atom][thread]).
+// Each atom pair (a < c) evaluates f3 once: s(mu_ac) multiplies P_a and
+// s(mu_ca) = s(-mu_ac) multiplies P_c, so every P_a receives its factors in
+// ascending order of the other atom.
+__global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mols, const double* __restrict__ Rat,
+                                                  const double* __restrict__ radial, const double* __restrict__ ang,
+                                                  int nrad, int nth, int nph, double* __restrict__ out)
 {
     const int m = blockIdx.y;
     const MolDesc md = mols[m];
     const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
     extern __shared__ double smem_grid[];
     const int na = md.natom;
+    const int bs = blockDim.x, t = threadIdx.x;
     double* Ra = smem_grid;                       // [natom][3]
     double* invR = Ra + 3 * na;                   // [natom][natom]: 1/|R_a - R_c|
-    double* dist = invR + na * na;                // [natom][blockDim]
+    double* dist = invR + na * na;                // [natom][bs]
+    double* Pc = dist + na * bs;                  // [natom][bs]
     for (int i = threadIdx.x; i < 3 * na; i += blockDim.x) Ra[i] = Rat[3 * md.atom0 + i];
     for (int i = threadIdx.x; i < na * na; i += blockDim.x) {
         const int a = i / na, c = i % na;
@@ -67,19 +75,20 @@ __global__ __launch_bounds__(128) void grid_kernel(const MolDesc* __restrict__ m
     p[0] = Ra[3 * A] + r * st * cos(ph);
     p[1] = Ra[3 * A + 1] + r * st * sin(ph);
     p[2] = Ra[3 * A + 2] + r * ct;
-    const int bs = blockDim.x, t = threadIdx.x;
-    for (int a = 0; a < md.natom; a++) {
+    for (int a = 0; a < na; a++) {
         const double dx = p[0] - Ra[3 * a], dy = p[1] - Ra[3 * a + 1], dz = p[2] - Ra[3 * a + 2];
         dist[a * bs + t] = sqrt(dx * dx + dy * dy + dz * dz);
+        Pc[a * bs + t] = 1.0;
     }
     double num = 0.0, den = 0.0;
     for (int a = 0; a < na; a++) {
         const double ra = dist[a * bs + t];
         const double* ir = invR + a * na;
-        double Pa = 1.0;
-        for (int c = 0; c < na && Pa > 0.0; c++) {
-            if (c == a) continue;
-            Pa *= becke_s((ra - dist[c * bs + t]) * ir[c]);
+        double Pa = Pc[a * bs + t];
+        for (int c = a + 1; c < na; c++) {
+            const double f = becke_f3((ra - dist[c * bs + t]) * ir[c]);
+            Pa *= 0.5 * (1.0 - f);
+            Pc[c * bs + t] *= 0.5 * (1.0 + f);
         }
         if (a == A) num = Pa;
         den += Pa;
@@ -101,14 +110,43 @@ ks_status launch_grid(ks_batch* b)
         maxg = std::max(maxg, m.ngrid);
         maxat = std::max(maxat, m.natom);
     }
-    const int bs = 128;
-    const size_t lds = sizeof(double) * (3 * maxat + (size_t)maxat * maxat + (size_t)maxat * bs);
+    int bs = 64;
+    auto lds_for = [&](int n) { return sizeof(double) * (3 * maxat + (size_t)maxat * maxat + 2 * (size_t)maxat * n); };
+    while (bs > 16 && lds_for(bs) > 163840) bs /= 2;
+    const size_t lds = lds_for(bs);
+    if (lds > 163840) {
+        set_error("grid: %d atoms exceed the LDS budget", maxat);
+        return KS_EUNSUPPORTED;
+    }
     KS_HIP(hipFuncSetAttribute((const void*)grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, b->stream,
                        b->d_mol, b->d_R, b->d_radial, b->d_ang, b->opt.n_rad, b->opt.n_theta, b->opt.n_phi, b->d_grid);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Elementary functions of the functional.  FP64: libm and IEEE division.
+// FP32 (the mixed path, whose tolerance is 1e-4 Ha): the hardware
+// reciprocal, square root, log2 and exp2 (about 1 ulp each); cbrt as
+// exp2(log2(x)/3), asinh as log(x + sqrt(x^2 + 1)) for x >= 0.
+// ---------------------------------------------------------------------------
+namespace fm {
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double log_(double x) { return log(x); }
+__device__ __forceinline__ float log_(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ __forceinline__ double exp_(double x) { return exp(x); }
+__device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ double cbrt_(double x) { return cbrt(x); }
+__device__ __forceinline__ float cbrt_(float x) { return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f)); }
+__device__ __forceinline__ double asinh_(double x) { return asinh(x); }
+__device__ __forceinline__ float asinh_(float x) { return log_(x + sqrt_(x * x + 1.0f)); }
+__device__ __forceinline__ double atan_(double x) { return atan(x); }
+__device__ __forceinline__ float atan_(float x) { return atanf(x); }
+}  // namespace fm
 
 // ---------------------------------------------------------------------------
 // B3LYP, closed shell: energy per volume e and v_rho = de/drho,
@@ -120,7 +158,7 @@ ks_status launch_grid(ks_batch* b)
 template <typename F>
 __device__ __forceinline__ void b3lyp_exchange(F rho, F sigma, F& e, F& vr, F& vs)
 {
-    const F r13 = cbrt(rho);
+    const F r13 = fm::cbrt_(rho);
     // Slater exchange, -(3/4)(3/pi)^(1/3) rho^(4/3)
     const F cs = F(0.7385587663820224);
     const F eS = -cs * rho * r13;
@@ -129,15 +167,17 @@ __device__ __forceinline__ void b3lyp_exchange(F rho, F sigma, F& e, F& vr, F& v
     const F beta = F(0.0042), Cx = F(0.9305257363491000);   // (3/2)(3/(4 pi))^(1/3)
     const F rs13 = r13 * F(0.7937005259840998);               // (rho/2)^(1/3)
     const F rs43 = F(0.5) * rho * rs13;
-    const F x = F(0.5) * sqrt(sigma) / rs43;
-    const F ash = asinh(x);
+    const F irs43 = fm::rcp(rs43);
+    const F x = F(0.5) * fm::sqrt_(sigma) * irs43;
+    const F ash = fm::asinh_(x);
     const F D = F(1) + F(6) * beta * x * ash;
-    const F Dp = F(6) * beta * (ash + x / sqrt(F(1) + x * x));
-    const F gx = x / D;                       // g(x)/x with g = x^2/D
-    const F gpx = (F(2) * D - x * Dp) / (D * D);   // g'(x)/x
+    const F iD = fm::rcp(D);
+    const F Dp = F(6) * beta * (ash + x * fm::rcp(fm::sqrt_(F(1) + x * x)));
+    const F gx = x * iD;                      // g(x)/x with g = x^2/D
+    const F gpx = (F(2) * D - x * Dp) * iD * iD;   // g'(x)/x
     const F eB = F(-2) * rs43 * (Cx + beta * x * gx);
     const F vB = F(-4.0 / 3.0) * rs13 * (Cx + beta * x * (gx - x * gpx));
-    const F sB = -beta * gpx / (F(4) * rs43);
+    const F sB = F(-0.25) * beta * gpx * irs43;
     e = F(0.08) * eS + F(0.72) * eB;
     vr = F(0.08) * vS + F(0.72) * vB;
     vs = F(0.72) * sB;
@@ -146,23 +186,23 @@ __device__ __forceinline__ void b3lyp_exchange(F rho, F sigma, F& e, F& vr, F& v
 template <typename F>
 __device__ __forceinline__ void b3lyp_vwn(F rho, int vwn5, F& e, F& vr, F& vs)
 {
-    const F pi = F(kPi);
-    // VWN (paramagnetic), x_v = sqrt(r_s)
+    // VWN (paramagnetic), x_v = sqrt(r_s), r_s = (3/(4 pi rho))^(1/3)
     F b, c, x0;
     if (vwn5) { b = F(3.72744); c = F(12.9352); x0 = F(-0.10498); }
     else { b = F(13.0720); c = F(42.7198); x0 = F(-0.409286); }
     const F Av = F(0.0310907);
-    const F rsv = cbrt(F(3) / (F(4) * pi * rho));
-    const F xv = sqrt(rsv);
-    const F X = xv * xv + b * xv + c, X0 = x0 * x0 + b * x0 + c, Q = sqrt(F(4) * c - b * b);
-    const F at = atan(Q / (F(2) * xv + b));
-    const F bxX0 = b * x0 / X0;
-    const F epsv = Av * (log(xv * xv / X) + F(2) * b / Q * at
-                         - bxX0 * (log((xv - x0) * (xv - x0) / X) + F(2) * (b + F(2) * x0) / Q * at));
-    const F deps = Av * (F(2) / xv - (F(2) * xv + b) / X - b / X
-                         - bxX0 * (F(2) / (xv - x0) - (F(2) * xv + b) / X - (b + F(2) * x0) / X));
+    const F rsv = F(0.6203504908994001) * fm::rcp(fm::cbrt_(rho));   // (3/(4 pi))^(1/3) rho^(-1/3)
+    const F xv = fm::sqrt_(rsv);
+    const F X = xv * xv + b * xv + c, X0 = x0 * x0 + b * x0 + c, Q = fm::sqrt_(F(4) * c - b * b);
+    const F iX = fm::rcp(X), iQ = fm::rcp(Q);
+    const F at = fm::atan_(Q * fm::rcp(F(2) * xv + b));
+    const F bxX0 = b * x0 * fm::rcp(X0);
+    const F epsv = Av * (fm::log_(xv * xv * iX) + F(2) * b * iQ * at
+                         - bxX0 * (fm::log_((xv - x0) * (xv - x0) * iX) + F(2) * (b + F(2) * x0) * iQ * at));
+    const F deps = Av * (F(2) * fm::rcp(xv) - (F(2) * xv + b) * iX - b * iX
+                         - bxX0 * (F(2) * fm::rcp(xv - x0) - (F(2) * xv + b) * iX - (b + F(2) * x0) * iX));
     e = F(0.19) * rho * epsv;
-    vr = F(0.19) * (epsv - xv * deps / F(6));
+    vr = F(0.19) * (epsv - xv * deps * F(1.0 / 6.0));
     vs = F(0);
 }
 
@@ -172,15 +212,16 @@ __device__ __forceinline__ void b3lyp_lyp(F rho, F sigma, F& e, F& vr, F& vs)
     // LYP, closed-shell gradient form; t = rho^(-1/3)
     const F la = F(0.04918), lb = F(0.132), lc = F(0.2533), ld = F(0.349);
     const F CF = F(2.8712340001881915);      // (3/10)(3 pi^2)^(2/3)
-    const F t = F(1) / cbrt(rho), den = F(1) + ld * t, Ee = exp(-lc * t) / den;
-    const F delta = lc * t + ld * t / den;
+    const F t = fm::rcp(fm::cbrt_(rho)), den = F(1) + ld * t, iden = fm::rcp(den);
+    const F Ee = fm::exp_(-lc * t) * iden;
+    const F delta = lc * t + ld * t * iden;
     const F t5 = t * t * t * t * t;          // rho^(-5/3)
     const F abE = la * lb * Ee;
-    const F eL = -la * rho / den - abE * CF * rho + abE / F(72) * t5 * sigma * (F(3) + F(7) * delta);
-    const F vL = -la / den - la * ld * t / (F(3) * den * den) - abE * CF * (F(1) + delta / F(3))
-                 + abE / F(72) * sigma * t5 / rho / F(3)
-                       * (F(7) * delta * delta - F(39) * delta - F(15) + F(7) * ld * ld * t * t / (den * den));
-    const F sL = abE / F(72) * t5 * (F(3) + F(7) * delta);
+    const F eL = -la * rho * iden - abE * CF * rho + abE * F(1.0 / 72.0) * t5 * sigma * (F(3) + F(7) * delta);
+    const F vL = -la * iden - la * ld * t * F(1.0 / 3.0) * iden * iden - abE * CF * (F(1) + delta * F(1.0 / 3.0))
+                 + abE * F(1.0 / 216.0) * sigma * t5 * fm::rcp(rho)
+                       * (F(7) * delta * delta - F(39) * delta - F(15) + F(7) * ld * ld * t * t * iden * iden);
+    const F sL = abE * F(1.0 / 72.0) * t5 * (F(3) + F(7) * delta);
     e = F(0.81) * eL;
     vr = F(0.81) * vL;
     vs = F(0.81) * sL;

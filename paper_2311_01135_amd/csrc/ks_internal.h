@@ -23,6 +23,15 @@ constexpr double kRhoCut = 1e-12;      // points below this density carry no XC
 // Fock matrix carries ~1e-6 noise, below which FP32 cannot resolve changes.
 constexpr double kMixedETol = 1e-6;
 constexpr double kMixedCommTol = 1e-5;
+// Primitive ERI screening: a primitive quartet is skipped when its Gaussian
+// prefactor 2 pi^(5/2) K_ab K_cd / (p q sqrt(p + q)) is below the cut (far
+// below the FP64 parity tolerance, resp. the FP32 storage rounding).  kQMin
+// bounds p, q from below (twice the smallest STO-3G exponent, 0.1689 of H)
+// and kKMax bounds |K| from above (the largest is 26, F 1s with itself).
+constexpr double kEriCutFp64 = 1e-20;
+constexpr double kEriCutMixed = 1e-14;
+constexpr double kQMin = 0.3;
+constexpr double kKMax = 30.0;
 
 // Boys-function table: F_m(T_i), T_i = i * kBoysDT, i < kBoysNT, m < kBoysM.
 constexpr double kBoysDT = 0.05;
