@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 XC_SHAPES = [(64, 8), (64, 16), (32, 8), (32, 16), (16, 8), (64, 4), (32, 4)]
-XC_CHUNKS = [4, 8, 16, 32]
+XC_CHUNKS = [16, 32, 64]
 JK_CHUNKS = [2, 4, 8, 16]
 
 

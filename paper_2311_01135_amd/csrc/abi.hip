@@ -396,6 +396,13 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
                 if (la + lb == 1) pairs[1].push_back(la ? Pair{sa, sb} : Pair{sb, sa});
                 else pairs[la + lb].push_back(Pair{sa, sb});
             }
+        // anti-diagonal order (sa + sb, then sa): neighbouring pairs differ in
+        // both shells, so lanes digesting neighbouring quartets scatter to
+        // different J/K rows and columns
+        for (int c = 0; c < 3; c++)
+            std::stable_sort(pairs[c].begin() + md.pair0[c], pairs[c].end(), [](const Pair& x, const Pair& y) {
+                return x.sa + x.sb != y.sa + y.sb ? x.sa + x.sb < y.sa + y.sb : x.sa < y.sa;
+            });
         for (int c = 0; c < 3; c++) md.npair[c] = (int)pairs[c].size() - md.pair0[c];
         for (int c = 0; c < kNClass; c++) {
             const long nb = md.npair[class_bra(c)], nk = md.npair[class_ket(c)];
@@ -469,6 +476,12 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     if ((st = upload(b, &b->d_xc_items, b->xc_items))) return st;
     if ((st = upload(b, &b->d_xc_first, xc_first))) return st;
     for (int c = 0; c < 3; c++) {
+        std::vector<int2> pao(pairs[c].size());
+        for (size_t i = 0; i < pairs[c].size(); i++) {
+            const Pair& pr = pairs[c][i];
+            pao[i] = make_int2(b->shells[pr.sa].ao | (pr.sa == pr.sb ? 1 << 16 : 0), b->shells[pr.sb].ao);
+        }
+        if ((st = upload(b, &b->d_pair_ao[c], pao))) return st;
         if ((st = upload(b, &b->d_pairs[c], pairs[c]))) return st;
         if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair * 5))) return st;
     }

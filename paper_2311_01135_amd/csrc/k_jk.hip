@@ -38,8 +38,7 @@ struct JkArgs {
     const MolDesc* mol;
     const MolState* state;
     const JkItem* items;
-    const Shell* shells;
-    const Pair* pairs[3];
+    const int2* pao[3];     // per pair of each pair class: (AO of sa | same shell << 16, AO of sb)
     const void* eri[kNClass];
     long nq[kNClass];
     const double* P;
@@ -48,6 +47,10 @@ struct JkArgs {
     long part_stride;       // np_max^2
     int only_active;
 };
+
+// 8 wavefronts per group: the LDS holds one molecule's P, J, K, so one group
+// fills a CU, and the waves hide the latency of the integral stream.
+constexpr int kJkThreads = 512;
 
 template <typename A>
 __device__ __forceinline__ void lds_add(A* p, A v)
@@ -67,18 +70,27 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
     const long lo = nq * chunk / nchunk, hi = nq * (chunk + 1) / nchunk;
     const S* __restrict__ eri = (const S*)g.eri[C];
     const long NQ = g.nq[C];
-    const Pair* pb = g.pairs[class_bra(C)];
-    const Pair* pk = g.pairs[class_ket(C)];
-    for (long q = lo + threadIdx.x; q < hi; q += blockDim.x) {
-        int i, j;
-        decode_quartet_jk(C, q, md.npair[class_ket(C)], i, j);
-        const Pair P1 = pb[md.pair0[class_bra(C)] + i], P2 = pk[md.pair0[class_ket(C)] + j];
-        const int oa = g.shells[P1.sa].ao, ob = g.shells[P1.sb].ao;
-        const int oc = g.shells[P2.sa].ao, od = g.shells[P2.sb].ao;
+    const int2* __restrict__ pb = g.pao[class_bra(C)] + md.pair0[class_bra(C)];
+    const int2* __restrict__ pk = g.pao[class_ket(C)] + md.pair0[class_ket(C)];
+    const int nket = md.npair[class_ket(C)];
+    const int step = blockDim.x;
+    int i = 0, j = 0;
+    if (lo + threadIdx.x < hi) decode_quartet_jk(C, lo + threadIdx.x, nket, i, j);
+    for (long q = lo + threadIdx.x; q < hi; q += step) {
+        const int2 P1 = pb[i], P2 = pk[j];
+        const int oa = P1.x & 0xffff, ob = P1.y, oc = P2.x & 0xffff, od = P2.y;
         A f = A(1);
-        if (P1.sa == P1.sb) f *= A(0.5);
-        if (P2.sa == P2.sb) f *= A(0.5);
+        if (P1.x >> 16) f *= A(0.5);
+        if (P2.x >> 16) f *= A(0.5);
         if (class_tri(C) && i == j) f *= A(0.5);
+        // the next quartet of this thread: (i, j) advanced by step in row-major
+        // order over the triangle (j <= i) or the rectangle (j < nket)
+        int i2 = i, j2 = j + step;
+        if (class_tri(C)) {
+            while (j2 > i2) { j2 -= i2 + 1; i2++; }
+        } else {
+            while (j2 >= nket) { j2 -= nket; i2++; }
+        }
         const long qg = md.q0[C] + q;
         A I[NCOMP];
 #pragma unroll
@@ -124,10 +136,27 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
                         kbd[b][d] += v * pac[a][c];
                     }
         const A f2 = A(2) * f;
+        // J_ab: the lanes of a wave usually share the bra pair; then the wave
+        // sums its contributions and one lane adds them (same-address LDS
+        // atomics would serialise)
+        const unsigned long long act = __ballot(1);
+        const unsigned long long same = __ballot(__builtin_amdgcn_readfirstlane(i) == i);
+        if (act == ~0ull && same == act) {
 #pragma unroll
-        for (int a = 0; a < NA; a++)
+            for (int a = 0; a < NA; a++)
 #pragma unroll
-            for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[a][b]);
+                for (int b = 0; b < NB; b++) {
+                    A v = f2 * jab[a][b];
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                    if ((threadIdx.x & 63) == 0) lds_add(&AJ[(oa + a) * N + ob + b], v);
+                }
+        } else {
+#pragma unroll
+            for (int a = 0; a < NA; a++)
+#pragma unroll
+                for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[a][b]);
+        }
 #pragma unroll
         for (int c = 0; c < NC; c++)
 #pragma unroll
@@ -146,11 +175,13 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
 #pragma unroll
             for (int d = 0; d < ND; d++) lds_add(&AK[(ob + b) * N + od + d], f * kbd[b][d]);
         }
+        i = i2;
+        j = j2;
     }
 }
 
 template <typename S, typename A>
-__global__ __launch_bounds__(256) void jk_kernel(JkArgs g)
+__global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
 {
     const JkItem it = g.items[blockIdx.x];
     if (g.only_active && g.state[it.mol].status != KS_MOL_ACTIVE) return;
@@ -243,8 +274,7 @@ static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool
     g.mol = b->d_mol;
     g.state = b->d_state;
     g.items = b->d_jk_items;
-    g.shells = b->d_shells;
-    for (int c = 0; c < 3; c++) g.pairs[c] = b->d_pairs[c];
+    for (int c = 0; c < 3; c++) g.pao[c] = b->d_pair_ao[c];
     for (int c = 0; c < kNClass; c++) {
         g.eri[c] = b->d_eri[c];
         g.nq[c] = b->nq[c];
@@ -258,7 +288,7 @@ static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool
     KS_HIP(hipFuncSetAttribute((const void*)jk_kernel<S, A>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     {
         KTimer tm(b, "jk");
-        hipLaunchKernelGGL((jk_kernel<S, A>), dim3((unsigned)b->jk_items.size()), dim3(256), lds, b->stream, g);
+        hipLaunchKernelGGL((jk_kernel<S, A>), dim3((unsigned)b->jk_items.size()), dim3(kJkThreads), lds, b->stream, g);
     }
     KS_HIP(hipGetLastError());
     KTimer tr(b, "jk_reduce");

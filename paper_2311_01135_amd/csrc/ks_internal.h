@@ -142,6 +142,7 @@ struct ks_batch {
     double* d_R = nullptr;          // atom positions (bohr)
     double* d_Zc = nullptr;         // atom charges
     ks::Pair* d_pairs[3] = {nullptr, nullptr, nullptr};
+    int2* d_pair_ao[3] = {nullptr, nullptr, nullptr};  // per pair: (AO of sa | (sa == sb) << 16, AO of sb)
     double* d_pp[3] = {nullptr, nullptr, nullptr};   // [5][9][npair] primitive-pair tables
     long* d_qoff[ks::kNClass] = {};  // prefix over molecules (n_mol + 1)
     void* d_eri[ks::kNClass] = {};   // component-major, FP64 or FP32
