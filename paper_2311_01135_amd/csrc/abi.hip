@@ -24,12 +24,12 @@ void set_error(const char* fmt, ...)
     va_end(ap);
 }
 
-KTimer::KTimer(ks_batch* b_, const char* n) : b(b_), name(n)
+KTimer::KTimer(ks_batch* b_, const char* n, hipStream_t s_) : b(b_), name(n), s(s_)
 {
     if (b->timing) {
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
-        (void)hipEventRecord(e0, b->stream);
+        (void)hipEventRecord(e0, s);
     }
 }
 
@@ -38,7 +38,7 @@ KTimer::KTimer(ks_batch* b_, const char* n) : b(b_), name(n)
 KTimer::~KTimer()
 {
     if (!b->timing) return;
-    (void)hipEventRecord(e1, b->stream);
+    (void)hipEventRecord(e1, s);
     int idx = -1;
     for (size_t i = 0; i < b->tnames.size(); i++)
         if (b->tnames[i] == name) idx = (int)i;
@@ -195,10 +195,14 @@ static ks_status upload(ks_batch* b, T** p, const std::vector<T>& v)
 static void free_batch(ks_batch* b)
 {
     if (!b) return;
+    if (b->aux) (void)hipStreamSynchronize(b->aux);
     resolve_timers(b);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     else (void)hipDeviceSynchronize();
     for (void* p : b->allocs) (void)hipFree(p);
+    if (b->ev_grid) (void)hipEventDestroy(b->ev_grid);
+    if (b->ev_main) (void)hipEventDestroy(b->ev_main);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
     if (b->h_nactive) (void)hipHostFree(b->h_nactive);
     delete b;
 }
@@ -462,6 +466,9 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         pt += (long)md.np * md.np;
     }
     b->npt_total = pt;
+    KS_HIP(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking));
+    KS_HIP(hipEventCreateWithFlags(&b->ev_main, hipEventDisableTiming));
+    KS_HIP(hipEventCreateWithFlags(&b->ev_grid, hipEventDisableTiming));
     if ((st = upload(b, &b->d_mol, b->mol))) return st;
     if ((st = upload(b, &b->d_shells, b->shells))) return st;
     if ((st = upload(b, &b->d_aoinfo, aoinfo))) return st;
@@ -581,7 +588,11 @@ ks_status ks_setup(ks_batch* b)
         }
     if (b->opt.xc != KS_XC_HF) {
         if ((st = dev_alloc(b, &b->d_grid, 4 * (size_t)b->ngrid))) return st;
-        if ((st = launch_grid(b))) return st;
+        KS_HIP(hipEventRecord(b->ev_main, b->stream));
+        KS_HIP(hipStreamWaitEvent(b->aux, b->ev_main, 0));
+        if ((st = launch_grid(b, b->aux))) return st;
+        KS_HIP(hipEventRecord(b->ev_grid, b->aux));
+        b->grid_pending = true;
     }
     if ((st = launch_guess(b))) return st;
     b->setup_done = true;
@@ -664,6 +675,19 @@ ks_status fock_build(ks_batch* b, const void* Pin, void* F, double* E_terms)
 }
 
 }  // extern "C"
+
+namespace ks {
+
+ks_status grid_wait(ks_batch* b)
+{
+    if (b->grid_pending) {
+        KS_HIP(hipStreamWaitEvent(b->stream, b->ev_grid, 0));
+        b->grid_pending = false;
+    }
+    return KS_OK;
+}
+
+}  // namespace ks
 
 namespace ks {
 
@@ -803,6 +827,8 @@ ks_status ks_get_grid(const ks_batch* b, int mol, double* out)
         return KS_ESTATE;
     }
     const MolDesc& md = b->mol[mol];
+    ks_status st = grid_wait(const_cast<ks_batch*>(b));
+    if (st) return st;
     KS_HIP(hipMemcpyAsync(out, b->d_grid + 4 * md.grid0, sizeof(double) * 4 * md.ngrid, hipMemcpyDeviceToHost, b->stream));
     KS_HIP(hipStreamSynchronize(b->stream));
     return KS_OK;

@@ -101,9 +101,9 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
     o[3] = w;
 }
 
-ks_status launch_grid(ks_batch* b)
+ks_status launch_grid(ks_batch* b, hipStream_t s)
 {
-    KTimer tm(b, "grid");
+    KTimer tm(b, "grid", s);
     long maxg = 0;
     int maxat = 0;
     for (auto& m : b->mol) {
@@ -119,7 +119,7 @@ ks_status launch_grid(ks_batch* b)
         return KS_EUNSUPPORTED;
     }
     KS_HIP(hipFuncSetAttribute((const void*)grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, b->stream,
+    hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, s,
                        b->d_mol, b->d_R, b->d_radial, b->d_ang, b->opt.n_rad, b->opt.n_theta, b->opt.n_phi, b->d_grid);
     KS_HIP(hipGetLastError());
     return KS_OK;
@@ -777,6 +777,8 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
 
 ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active)
 {
+    ks_status st = grid_wait(b);
+    if (st) return st;
     if (b->opt.prec == KS_MIXED) return run_xc<float>(b, P, V, only_active);
     return run_xc<double>(b, P, V, only_active);
 }

@@ -21,10 +21,14 @@ void set_error(const char* fmt, ...);
 struct KTimer {
     ks_batch* b;
     const char* name;
+    hipStream_t s;
     hipEvent_t e0{}, e1{};
-    KTimer(ks_batch* b_, const char* n);
+    KTimer(ks_batch* b_, const char* n, hipStream_t s_);
+    KTimer(ks_batch* b_, const char* n) : KTimer(b_, n, b_->stream) {}
     ~KTimer();
 };
+// Makes the batch stream wait for a grid still being built on the aux stream.
+ks_status grid_wait(ks_batch* b);
 void resolve_timers(ks_batch* b);
 
 // integrals (k_ints.hip)
@@ -42,7 +46,7 @@ size_t jk_lds_bytes(const ks_batch* b);
 bool jk_acc_fp64(const ks_batch* b);
 
 // grid and XC (k_xc.hip)
-ks_status launch_grid(ks_batch* b);
+ks_status launch_grid(ks_batch* b, hipStream_t s);
 ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active);
 size_t xc_lds_bytes(const ks_batch* b);
 int xc_block_points(const ks_batch* b);

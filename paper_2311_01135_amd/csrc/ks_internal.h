@@ -118,6 +118,12 @@ struct JkItem {
 struct ks_batch {
     ks_options opt;
     hipStream_t stream = nullptr;
+    // The grid and Becke weights are built on a second stream while the ERIs
+    // run on the batch stream; the batch stream waits on ev_grid before the
+    // first use of the grid.
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_main = nullptr, ev_grid = nullptr;
+    bool grid_pending = false;
     int n_mol = 0;
     int max_np = 0;
     int max_nshell = 0;
