@@ -157,6 +157,17 @@ ks_status scf_step(ks_batch* b, int* n_active);
  * still returns KS_OK. */
 ks_status scf_solve(ks_batch* b);
 
+/* scf_solve for n batches at once: every round queues one SCF iteration of
+ * each batch that still has active molecules on that batch's own stream,
+ * then waits for them in order, so the batches' kernels overlap on the GPU
+ * (a batch's small per-molecule steps run beside another batch's XC and J/K
+ * work).  Batches must be distinct and should use distinct streams
+ * (ks_batch_create's stream argument); on a shared stream the result is the
+ * same, only without overlap.  Molecules are independent, so each batch's
+ * results equal those of scf_solve on it alone.  Returns the first error of
+ * any batch (KS_EINVAL for NULL arguments or n <= 0). */
+ks_status scf_solve_many(ks_batch* const* batches, int n);
+
 /* Results of molecule mol (host buffers; eps[nbf] and P[nbf*nbf] may be
  * NULL).  gap = eps_LUMO - eps_HOMO (> 0); eps are the eigenvalues of the
  * last un-extrapolated Fock matrix and P the density that produced it. */

@@ -94,14 +94,14 @@ def _time_jk(ks, mols, prec, chunks, reps):
     return ms
 
 
-def tune(ks, mols, prec, reps=3, log=print):
+def tune(ks, mols, prec, reps=3, log=print, shapes=None, xc_chunks=None, jk_chunks=None):
     res = {"xc": [], "jk": []}
-    for pts, waves in XC_SHAPES:
-        for ch in XC_CHUNKS:
+    for pts, waves in shapes or XC_SHAPES:
+        for ch in xc_chunks or XC_CHUNKS:
             ms = _time_xc(ks, mols, prec, pts, waves, ch, reps)
             res["xc"].append(dict(xc_points=pts, xc_waves=waves, xc_chunks=ch, ms=ms))
             log("xc points %2d waves %d chunks %2d: %.2f ms" % (pts, waves, ch, ms))
-    for ch in JK_CHUNKS:
+    for ch in jk_chunks or JK_CHUNKS:
         ms = _time_jk(ks, mols, prec, ch, reps)
         res["jk"].append(dict(jk_chunks=ch, ms=ms))
         log("jk chunks %2d: %.2f ms" % (ch, ms))
@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--xc-shapes", default="", help="points x waves list, e.g. 64x16,64x8 (default: all)")
+    ap.add_argument("--xc-chunks", default="", help="work groups per molecule list, e.g. 32,64 (default: all)")
+    ap.add_argument("--jk-chunks", default="", help="J/K work groups per molecule list (default: all)")
     a = ap.parse_args()
     sys.path.insert(0, ROOT)
     import torch
@@ -128,7 +131,11 @@ def main():
     lo, hi = (int(v) for v in a.heavy.split("-")) if "-" in a.heavy else (int(a.heavy),) * 2
     mols = molgen.batch(a.n_mol, a.seed, (lo, hi) if lo != hi else lo)
     prec = 1 if a.prec == "mixed" else 0
-    best, res = tune(ks, mols, prec, a.reps, log=lambda s: print(s, flush=True))
+    shapes = [tuple(int(v) for v in t.split("x")) for t in a.xc_shapes.split(",")] if a.xc_shapes else None
+    xcc = [int(v) for v in a.xc_chunks.split(",")] if a.xc_chunks else None
+    jkc = [int(v) for v in a.jk_chunks.split(",")] if a.jk_chunks else None
+    best, res = tune(ks, mols, prec, a.reps, log=lambda s: print(s, flush=True), shapes=shapes, xc_chunks=xcc,
+                     jk_chunks=jkc)
     nbf = [molgen.nbf_sto3g(z) for z, _ in mols]
     table = load_table(a.out)
     table[key(prec, max(nbf), len(mols))] = dict(best, workload="%d x %s heavy, seed %d" % (a.n_mol, a.heavy, a.seed))

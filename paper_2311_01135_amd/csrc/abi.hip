@@ -730,6 +730,49 @@ ks_status scf_step(ks_batch* b, int* n_active)
     return step_finish(b, n_active);
 }
 
+ks_status scf_solve_many(ks_batch* const* bs, int n)
+{
+    if (!bs || n <= 0) {
+        set_error("scf_solve_many: NULL batch list or n <= 0");
+        return KS_EINVAL;
+    }
+    for (int i = 0; i < n; i++) {
+        CHECK_B(bs[i]);
+        for (int k = 0; k < i; k++)
+            if (bs[k] == bs[i]) {
+                set_error("scf_solve_many: batch %d appears twice", i);
+                return KS_EINVAL;
+            }
+    }
+    // each batch's next iteration is queued as soon as its previous one has
+    // been read back, so the GPU always holds work of the other batches
+    std::vector<char> active(n, 1);
+    std::vector<int> steps(n, 0);
+    ks_status st;
+    for (int i = 0; i < n; i++) {
+        if ((st = step_launch(bs[i]))) return st;
+        steps[i] = 1;
+    }
+    for (int left = n; left > 0;) {
+        for (int i = 0; i < n; i++) {
+            if (!active[i]) continue;
+            int na = 0;
+            if ((st = step_finish(bs[i], &na))) return st;
+            if (na == 0) {
+                active[i] = 0;
+                left--;
+            } else if (steps[i] >= bs[i]->opt.max_iter + 2) {
+                set_error("scf_solve_many: batch %d still active after max_iter + 2 steps", i);
+                return KS_ESTATE;
+            } else {
+                if ((st = step_launch(bs[i]))) return st;
+                steps[i]++;
+            }
+        }
+    }
+    return KS_OK;
+}
+
 ks_status scf_solve(ks_batch* b)
 {
     CHECK_B(b);

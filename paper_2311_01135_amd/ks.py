@@ -26,8 +26,8 @@ STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", 
                 -5: "KS_EUNSUPPORTED", -6: "KS_ESTATE"}
 
 EXPORTS = ["ks_default_options", "ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup",
-           "eri_build", "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "ks_get_result",
-           "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence", "ks_kernel_times",
+           "eri_build", "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "scf_solve_many",
+           "ks_get_result", "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence", "ks_kernel_times",
            "ks_kernel_counts", "ks_set_timing",
            "ks_batch_destroy", "ks_last_error", "ks_server_create", "ks_server_submit",
            "ks_server_progress", "ks_server_poll", "ks_server_stats", "ks_server_destroy"]
@@ -69,6 +69,7 @@ def load():
     L.xc_build.argtypes = [vp, vp, vp, dp]
     L.fock_build.argtypes = [vp, vp, vp, dp]
     L.scf_step.argtypes = [vp, ip]
+    L.scf_solve_many.argtypes = [C.POINTER(vp), C.c_int]
     L.ks_get_result.argtypes = [vp, C.c_int, dp, dp, dp, dp, dp, dp, ip, ip]
     L.ks_get_eri.argtypes = [vp, C.c_int, dp]
     L.ks_get_matrix.argtypes = [vp, C.c_int, C.c_int, dp]
@@ -93,7 +94,7 @@ def load():
         getattr(L, name).restype = C.c_int
     L.ks_last_error.restype = C.c_char_p
     for name in ("ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup", "eri_build",
-                 "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "ks_get_result",
+                 "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "scf_solve_many", "ks_get_result",
                  "ks_get_eri", "ks_get_matrix", "ks_get_grid"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -119,6 +120,13 @@ def default_options(**kw) -> Options:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def solve_many(batches):
+    """scf_solve over several batches at once (each on its own stream, so their
+    kernels overlap); same results as solving each alone."""
+    arr = (C.c_void_p * len(batches))(*[b.h for b in batches])
+    _check(load().scf_solve_many(arr, len(batches)))
 
 
 class Batch:

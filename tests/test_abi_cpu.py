@@ -83,6 +83,9 @@ def test_rejects_too_large_fp64(lib):
 def test_null_handle_calls(lib):
     assert lib.eri_build(None) == -1
     assert lib.scf_solve(None) == -1
+    assert lib.scf_solve_many(None, 1) == -1
+    arr = (C.c_void_p * 2)(None, None)
+    assert lib.scf_solve_many(arr, 2) == -1
     lib.ks_batch_destroy(None)
 
 

@@ -76,3 +76,32 @@ def test_tiny_budget_serialises(ks):
     mols = _mols()[:4]
     served, peak = _serve(ks, mols, budget=1 << 20)
     assert all(r is not None and r["status"] == 1 for r in served)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_many_equals_separate(ks, prec):
+    """scf_solve_many over three batches on three streams matches solving each
+    batch by itself (molecules are independent; the J/K scatter uses LDS
+    atomics, so agreement is to the alone-vs-mix tolerances)."""
+    mols = _mols()
+    parts = [mols[0:3], mols[3:6], mols[6:8]]
+    ref = []
+    for p in parts:
+        with ks.Batch(p, prec=prec, jk_chunks=8, xc_chunks=16) as b:
+            b.scf_solve()
+            ref.append([b.result(m) for m in range(b.n_mol)])
+    streams = [torch.cuda.Stream() for _ in parts]
+    bs = [ks.Batch(p, prec=prec, jk_chunks=8, xc_chunks=16, stream=s.cuda_stream) for p, s in zip(parts, streams)]
+    try:
+        ks.solve_many(bs)
+        for b, r in zip(bs, ref):
+            for m in range(b.n_mol):
+                got = b.result(m)
+                tol = 1e-10 if prec == 0 else 1e-6
+                assert got["status"] == r[m]["status"] == 1
+                assert abs(got["E"] - r[m]["E"]) <= tol and abs(got["gap"] - r[m]["gap"]) <= tol
+                if prec == 0:
+                    assert got["n_iter"] == r[m]["n_iter"]
+    finally:
+        for b in bs:
+            b.close()
