@@ -58,17 +58,44 @@ __device__ double block_max(double v, double* red)
 }
 
 // C = op(A) op(B), N x N, global memory (L2-resident); ends with a barrier.
+// C = op(A) op(B) for N x N row-major matrices: both operands are staged in
+// LDS (sm: 2 N^2 + 4 doubles), each thread forms four adjacent outputs of a
+// row; every output sums over k in ascending order.  C may alias A or B.
 __device__ void wg_matmul(int N, const double* __restrict__ A, bool ta, const double* __restrict__ B, bool tb,
-                          double* __restrict__ C)
+                          double* C, double* sm)
 {
+    double* As = sm;             // op(A), row-major
+    double* Bs = sm + N * N;     // op(B), row-major (+4 doubles of slack for the last column block)
     for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
-        const int i = t / N, j = t % N;
-        double s = 0.0;
-        for (int k = 0; k < N; k++) s += (ta ? A[k * N + i] : A[i * N + k]) * (tb ? B[j * N + k] : B[k * N + j]);
-        C[t] = s;
+        const int r = t / N, c = t % N;
+        As[t] = ta ? A[c * N + r] : A[t];
+        Bs[t] = tb ? B[c * N + r] : B[t];
+    }
+    if (threadIdx.x < 4) Bs[N * N + threadIdx.x] = 0.0;
+    __syncthreads();
+    const int nb = (N + 3) / 4;
+    for (int t = threadIdx.x; t < N * nb; t += blockDim.x) {
+        const int i = t / nb, j0 = (t % nb) * 4;
+        const double* ar = As + i * N;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int k = 0; k < N; k++) {
+            const double a = ar[k];
+            const double* br = Bs + k * N + j0;
+            s0 += a * br[0];
+            s1 += a * br[1];
+            s2 += a * br[2];
+            s3 += a * br[3];
+        }
+        double* cr = C + i * N + j0;
+        cr[0] = s0;
+        if (j0 + 1 < N) cr[1] = s1;
+        if (j0 + 2 < N) cr[2] = s2;
+        if (j0 + 3 < N) cr[3] = s3;
     }
     __syncthreads();
 }
+
+extern __shared__ __align__(16) double smem_scf[];   // 2 N_max^2 + 4 doubles for wg_matmul
 
 struct ScfArgs {
     const MolDesc* mol;
@@ -181,15 +208,15 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
     const double *F = g.F + o, *P = g.P + o, *S = g.S + o, *X = g.X + o;
     double *W0 = g.work + o, *W1 = g.work + g.nmat + o, *W2 = g.work + 2 * g.nmat + o;
     const int it = st.iter + 1;
-    wg_matmul(N, F, false, P, false, W0);
-    wg_matmul(N, W0, false, S, false, W1);     // FPS
+    wg_matmul(N, F, false, P, false, W0, smem_scf);
+    wg_matmul(N, W0, false, S, false, W1, smem_scf);     // FPS
     for (int t = threadIdx.x; t < NN; t += blockDim.x) {
         const int i = t / N, j = t % N;
         W0[t] = W1[i * N + j] - W1[j * N + i];
     }
     __syncthreads();
-    wg_matmul(N, X, true, W0, false, W2);
-    wg_matmul(N, W2, false, X, false, W0);     // e
+    wg_matmul(N, X, true, W0, false, W2, smem_scf);
+    wg_matmul(N, W2, false, X, false, W0, smem_scf);     // e
     double mx = 0.0;
     for (int t = threadIdx.x; t < NN; t += blockDim.x) mx = fmax(mx, fabs(W0[t]));
     const double err = block_max(mx, red);
@@ -250,8 +277,8 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
         __syncthreads();
         Fsrc = W1;
     }
-    wg_matmul(N, X, true, Fsrc, false, W2);
-    wg_matmul(N, W2, false, X, false, g.Fp + o);
+    wg_matmul(N, X, true, Fsrc, false, W2, smem_scf);
+    wg_matmul(N, W2, false, X, false, g.Fp + o, smem_scf);
     if (threadIdx.x == 0) {
         st.iter = it;
         st.err = err;
@@ -292,8 +319,8 @@ __global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const doub
     const int m = blockIdx.x;
     const MolDesc md = g.mol[m];
     const long o = md.mat0;
-    wg_matmul(md.nbf, g.X + o, true, A + o, false, g.work + o);
-    wg_matmul(md.nbf, g.work + o, false, g.X + o, false, g.Fp + o);
+    wg_matmul(md.nbf, g.X + o, true, A + o, false, g.work + o, smem_scf);
+    wg_matmul(md.nbf, g.work + o, false, g.X + o, false, g.Fp + o, smem_scf);
 }
 
 // Symmetric eigenproblem, parallel-order cyclic Jacobi (round-robin pairing:
@@ -462,12 +489,15 @@ __global__ __launch_bounds__(kScfThreads) void density_kernel(ScfArgs g, int gue
     const int N = md.nbf, no = md.nocc;
     const long o = md.mat0;
     const int fin = guess ? 0 : st.final_;
-    wg_matmul(N, g.X + o, false, g.Fp + o, false, g.C + o);   // Fp holds C' here
+    wg_matmul(N, g.X + o, false, g.Fp + o, false, g.C + o, smem_scf);   // Fp holds C' here
     if (!fin) {
+        double* Cs = smem_scf;
+        for (int t = threadIdx.x; t < N * N; t += blockDim.x) Cs[t] = g.C[o + t];
+        __syncthreads();
         for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
             const int i = t / N, j = t % N;
             double s = 0.0;
-            for (int k = 0; k < no; k++) s += g.C[o + i * N + k] * g.C[o + j * N + k];
+            for (int k = 0; k < no; k++) s += Cs[i * N + k] * Cs[j * N + k];
             g.P[o + t] = 2.0 * s;
         }
     }
@@ -510,6 +540,14 @@ static ScfArgs scf_args(ks_batch* b, bool only_active)
     g.diis_space = b->opt.diis_space;
     g.only_active = only_active;
     return g;
+}
+
+// dynamic LDS of the kernels that call wg_matmul
+static size_t matmul_lds(const ks_batch* b)
+{
+    int maxn = 0;
+    for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
+    return sizeof(double) * (2 * (size_t)maxn * maxn + 4);
 }
 
 static size_t eigh_lds(const ks_batch* b)
@@ -567,11 +605,13 @@ ks_status launch_guess(ks_batch* b)
         return KS_OK;
     }
     ScfArgs g = scf_args(b, false);
-    hipLaunchKernelGGL(xtax_kernel, dim3(b->n_mol), dim3(kScfThreads), 0, b->stream, g, (const double*)b->d_H);
+    KS_HIP(hipFuncSetAttribute((const void*)xtax_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
+    hipLaunchKernelGGL(xtax_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g, (const double*)b->d_H);
     KS_HIP(hipGetLastError());
     ks_status st = run_eigh(b, false, b->d_Fp, b->d_Fp, b->d_eps);
     if (st) return st;
-    hipLaunchKernelGGL(density_kernel, dim3(b->n_mol), dim3(kScfThreads), 0, b->stream, g, 1);
+    KS_HIP(hipFuncSetAttribute((const void*)density_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
+    hipLaunchKernelGGL(density_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g, 1);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
@@ -581,7 +621,8 @@ ks_status launch_iteration_tail(ks_batch* b)
     ScfArgs g = scf_args(b, true);
     {
         KTimer tm(b, "diis");
-        hipLaunchKernelGGL(diis_kernel, dim3(b->n_mol), dim3(kScfThreads), 0, b->stream, g);
+        KS_HIP(hipFuncSetAttribute((const void*)diis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
+        hipLaunchKernelGGL(diis_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g);
         KS_HIP(hipGetLastError());
     }
     {
@@ -591,7 +632,8 @@ ks_status launch_iteration_tail(ks_batch* b)
     }
     {
         KTimer tm(b, "density");
-        hipLaunchKernelGGL(density_kernel, dim3(b->n_mol), dim3(kScfThreads), 0, b->stream, g, 0);
+        KS_HIP(hipFuncSetAttribute((const void*)density_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
+        hipLaunchKernelGGL(density_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g, 0);
         KS_HIP(hipGetLastError());
     }
     return KS_OK;
