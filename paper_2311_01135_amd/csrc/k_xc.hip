@@ -296,7 +296,8 @@ struct ShellLds {
 // shell table, per-point density and gradient, the three functional parts,
 // the per-AO-tile density partials, the padded density P (row stride NP + 4)
 // and four AO-major planes [AO][point] (row stride BP + 4): Phi, d/dx Phi
-// (overwritten by W once the density is formed), d/dy Phi, d/dz Phi.
+// (overwritten by W once the density is formed), d/dy Phi, d/dz Phi; the
+// FP32 path adds a fifth, Phi as bf16 pairs.
 __host__ __device__ constexpr size_t al32(size_t x) { return (x + 31) & ~(size_t)31; }
 __host__ __device__ constexpr int xc_ldp(int np) { return np + 4; }
 __host__ __device__ constexpr int xc_ldg(int bp) { return bp + 4; }
@@ -304,11 +305,41 @@ __host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw,
 {
     return al32((size_t)bp * 4 * sizeof(double)) + al32((size_t)nw * sizeof(double))
            + al32((size_t)ns * 3 * sizeof(double)) + al32((size_t)ns * 6 * es) + al32((size_t)bp * 4 * es)
-           + al32((size_t)bp * 9 * es) + al32((size_t)(np / 16) * 4 * bp * es) + al32((size_t)np * xc_ldp(np) * es)
-           + al32((size_t)4 * np * xc_ldg(bp) * es) + al32((size_t)ns * sizeof(int));
+           + al32((size_t)bp * 9 * es) + al32((size_t)(np / 16) * 4 * bp * es)
+           + al32((size_t)np * xc_ldp(np) * es)
+           + al32((size_t)(es == sizeof(float) ? 5 : 4) * np * xc_ldg(bp) * es) + al32((size_t)ns * sizeof(int));
 }
 
 constexpr size_t kLdsMax = 163840;
+
+// ---------------------------------------------------------------------------
+// FP32 path: AO values and W are held as split pairs x = hi + lo of bf16
+// values (hi = bf16(x), lo = bf16(x - hi); |x - hi - lo| <= 2^-17 |x|), one
+// 32-bit word per element with hi in the low half.  A 16x16x32 bf16 MFMA over
+// pair-interleaved operands sums hi*hi + lo*lo; a second one with one
+// operand's halves swapped adds hi*lo + lo*hi, so two MFMAs form the exact
+// product of the two pairs (fp32 accumulation) for 16 k at a time, against
+// four 16x16x4 FP32 MFMAs at a quarter of the rate.  Only V_XC = Phi^T W + ...
+// uses it.  The density and E_XC keep FP32 AO values and FP32 MFMAs: rounding
+// P would perturb every point alike (a ~1e-5 Fock-matrix error that stalls
+// the SCF at the mixed-path thresholds), and rounding Phi, which repeats on
+// each radial shell, biases E_XC by ~1e-5 Ha.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned int bf16_pair(float x)
+{
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    return (unsigned int)__builtin_bit_cast(unsigned short, h) | ((unsigned int)__builtin_bit_cast(unsigned short, l) << 16);
+}
+__device__ __forceinline__ unsigned int pair_swap(unsigned int w) { return (w >> 16) | (w << 16); }
+__device__ __forceinline__ f4_t mfma_pair(u32x4_t a, u32x4_t b, f4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                    c, 0, 0, 0);
+}
 
 // The MFMA k index runs over 16-wide blocks: within a block, lane group
 // q = lane / 16 supplies k = 4 q + j to the j-th of four MFMAs, so a lane's
@@ -342,9 +373,8 @@ __device__ __forceinline__ void gemm_x_rho(const T* __restrict__ Pl, const T* __
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
             a[j] = *(const V*)(Pl + pa[j] + kk);
-            const T* pbk = Phi + pb[j] + kk * LDG;
 #pragma unroll
-            for (int i = 0; i < 4; i++) bv[j][i] = pbk[i * LDG];
+            for (int i = 0; i < 4; i++) bv[j][i] = Phi[pb[j] + (kk + i) * LDG];
         }
 #pragma unroll
         for (int i = 0; i < 4; i++)
@@ -413,6 +443,40 @@ __device__ __forceinline__ void gemm_phit_w(const T* __restrict__ Phi, const T* 
     }
 }
 
+// acc[j] += tile of Phi^T W from the Phi and W pair planes (both AO-major).
+template <int NW, int BP, int MAXT, int NJ>
+__device__ __forceinline__ void gemm_phit_w_pair(const unsigned int* __restrict__ Phi, const unsigned int* __restrict__ Wt,
+                                                 int LDG, int NT, int wave, int lane, f4_t (&acc)[MAXT])
+{
+    if constexpr (NJ <= MAXT) {
+        const int l16 = lane & 15, q = lane >> 4;
+        int pa[NJ], pb[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            const int t = wave + j * NW;
+            pa[j] = ((t / NT) * 16 + l16) * LDG + 4 * q;
+            pb[j] = ((t % NT) * 16 + l16) * LDG + 4 * q;
+        }
+#pragma unroll
+        for (int kk = 0; kk < BP; kk += 16) {
+            u32x4_t a[NJ], bv[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; j++) {
+                a[j] = *(const u32x4_t*)(Phi + pa[j] + kk);
+                bv[j] = *(const u32x4_t*)(Wt + pb[j] + kk);
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; j++) {
+                u32x4_t bs;
+#pragma unroll
+                for (int i = 0; i < 4; i++) bs[i] = pair_swap(bv[j][i]);
+                acc[j] = mfma_pair(a[j], bv[j], acc[j]);
+                acc[j] = mfma_pair(a[j], bs, acc[j]);
+            }
+        }
+    }
+}
+
 template <typename T, int BP, int NW, int MAXT>
 __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
 {
@@ -450,9 +514,11 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     T* coef = (T*)take(BP * 4 * sizeof(T));                   // [BP][4]: rho, grad rho
     T* fpart = (T*)take(BP * 9 * sizeof(T));                  // [3][BP][3]: e, v_rho, v_sigma per part
     T* rpart = (T*)take((size_t)NT * 4 * BP * sizeof(T));     // [NT][4][BP]
+    constexpr bool kPair = sizeof(T) == 4;                    // FP32: Phi and W as bf16 pairs
     T* Pl = (T*)take((size_t)NP * LDP * sizeof(T));           // [NP][LDP]
-    T* Phi = (T*)take((size_t)4 * PL * sizeof(T));            // 4 planes [NP][LDG]
+    T* Phi = (T*)take((size_t)(kPair ? 5 : 4) * PL * sizeof(T));   // 4 (FP32: 5) planes [NP][LDG]
     T* Wt = Phi + PL;                                         // W^T overwrites d/dx Phi
+    unsigned int* Php = (unsigned int*)(Phi + 4 * PL);        // FP32: Phi as bf16 pairs
     shl.info = (int*)take((size_t)g.ns_max * sizeof(int));
 
     const T* __restrict__ Pt = (const T*)g.Pt + g.ptoff[m];
@@ -469,7 +535,7 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
         }
         shl.info[i] = S.ao | (S.L << 16);
     }
-    for (int i = tid; i < 4 * PL; i += NTH) Phi[i] = T(0);
+    for (int i = tid; i < (kPair ? 5 : 4) * PL; i += NTH) Phi[i] = T(0);
 
     V acc[MAXT];
 #pragma unroll
@@ -529,8 +595,12 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
                 }
                 const int info = shl.info[s], mu = info & 0xffff;
                 T* o = Phi + mu * LDG + gp;
+                auto put_phi = [&](int off, T v) {
+                    o[off] = v;
+                    if constexpr (kPair) Php[(o - Phi) + off] = bf16_pair(v);
+                };
                 if ((info >> 16) == 0) {
-                    o[0] = R;
+                    put_phi(0, R);
                     o[PL] = dR * dx;
                     o[2 * PL] = dR * dy;
                     o[3 * PL] = dR * dz;
@@ -538,7 +608,7 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
                     const T d[3] = {dx, dy, dz};
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        o[c * LDG] = d[c] * R;
+                        put_phi(c * LDG, d[c] * R);
 #pragma unroll
                         for (int k = 0; k < 3; k++)
                             o[(k + 1) * PL + c * LDG] = (k == c ? R : T(0)) + d[c] * d[k] * dR;
@@ -607,13 +677,34 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             const int cw = (NP + NG - 1) / NG, m0 = grp * cw, m1 = min(NP, m0 + cw);
             for (int mu = m0; mu < m1; mu++) {
                 T* o = Phi + mu * LDG + gp;
-                o[PL] = c0 * o[0] + c1 * o[PL] + c2 * o[2 * PL] + c3 * o[3 * PL];
+                if constexpr (kPair) {
+                    const float w = c0 * o[0] + c1 * o[PL] + c2 * o[2 * PL] + c3 * o[3 * PL];
+                    *(unsigned int*)(o + PL) = bf16_pair(w);
+                } else {
+                    o[PL] = c0 * o[0] + c1 * o[PL] + c2 * o[2 * PL] + c3 * o[3 * PL];
+                }
             }
         }
         __syncthreads();
         // A += Phi^T W   (NP x BP) . (BP x NP), this wave's tiles
         lane_g = lane;
         asm volatile("" : "+v"(lane_g));
+        if constexpr (kPair) {
+            const unsigned int* Pw = Php;
+            const unsigned int* Ww = (const unsigned int*)Wt;
+            switch (nj2) {
+            case 1: gemm_phit_w_pair<NW, BP, MAXT, 1>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 2: gemm_phit_w_pair<NW, BP, MAXT, 2>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 3: gemm_phit_w_pair<NW, BP, MAXT, 3>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 4: gemm_phit_w_pair<NW, BP, MAXT, 4>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 5: gemm_phit_w_pair<NW, BP, MAXT, 5>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 6: gemm_phit_w_pair<NW, BP, MAXT, 6>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 7: gemm_phit_w_pair<NW, BP, MAXT, 7>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 8: gemm_phit_w_pair<NW, BP, MAXT, 8>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            case 9: gemm_phit_w_pair<NW, BP, MAXT, 9>(Pw, Ww, LDG, NT, wave, lane_g, acc); break;
+            default: break;
+            }
+        } else
         switch (nj2) {
         case 1: gemm_phit_w<T, NW, BP, MAXT, 1>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
         case 2: gemm_phit_w<T, NW, BP, MAXT, 2>(Phi, Wt, LDG, NT, wave, lane_g, acc); break;
