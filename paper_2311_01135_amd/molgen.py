@@ -22,6 +22,9 @@ tree(n_heavy, seed, index)
     the same way.  A draw with a dead end or any pair closer than 0.9 A is
     rejected and redrawn from the same stream.  Every accepted molecule is
     neutral with 8*n_heavy + 2 electrons.
+conformers(Z, xyz, n_conf, seed, index)
+    Torsion-sampled geometries of one molecule (same atoms and bonds), see
+    the function.
 
 Random numbers: SplitMix64(seed * 2**32 + index) seeds xoshiro256**.
 """
@@ -223,6 +226,94 @@ def batch(n_mol: int, seed: int, n_heavy=9, start: int = 0):
         else:
             n = n_heavy
         out.append(tree(n, seed, i))
+    return out
+
+
+def bonds(Z, xyz):
+    """Bond list of a generated tree from its distances: heavy-heavy pairs
+    within 1.7 A and H-heavy pairs within 1.25 A (the generator places them at
+    1.40-1.52 A and 1.09 A; non-bonded pairs are at least 0.9 A apart and
+    farther than these cut-offs in practice for these trees)."""
+    Z = np.asarray(Z)
+    xyz = np.asarray(xyz, dtype=np.float64)
+    out = []
+    for i in range(len(Z)):
+        for j in range(i):
+            if Z[i] == 1 and Z[j] == 1:
+                continue
+            cut = 1.7 if (Z[i] > 1 and Z[j] > 1) else 1.25
+            if np.linalg.norm(xyz[i] - xyz[j]) < cut:
+                out.append((j, i))
+    return out
+
+
+def _side(n, bond_list, a, b):
+    """Atoms on b's side of bond (a, b) in a tree."""
+    adj = [[] for _ in range(n)]
+    for i, j in bond_list:
+        adj[i].append(j)
+        adj[j].append(i)
+    seen = {a, b}
+    stack = [b]
+    out = [b]
+    while stack:
+        u = stack.pop()
+        for v in adj[u]:
+            if v not in seen:
+                seen.add(v)
+                out.append(v)
+                stack.append(v)
+    return out
+
+
+def conformers(Z, xyz, n_conf: int, seed: int, index: int = 0, jitter: float = 0.02, max_tries: int = 200):
+    """n_conf geometries of one molecule with the same atoms and bond graph:
+    conformer 0 is xyz itself; conformer k > 0 turns, one after another, every
+    bond between two heavy atoms that both carry further atoms by a torsion
+    U(0, 2 pi) (the side of the later atom rotates about the bond axis; a
+    torsion that brings any pair closer than 0.9 A or changes the
+    distance-derived bond list is redrawn, and after max_tries/10 draws the
+    bond keeps its torsion), then moves every coordinate by U(-jitter, jitter)
+    A (redrawn under the same two conditions).  Stands in for the several
+    non-equilibrium conformers per molecule of the paper's dataset (section
+    4); the stream of conformer k is SplitMix64((seed + 0xC0F) * 2**32 +
+    index * 65536 + k)."""
+    Z = np.asarray(Z, dtype=np.int32)
+    xyz0 = np.asarray(xyz, dtype=np.float64)
+    n = len(Z)
+    bl = bonds(Z, xyz0)
+    deg = np.zeros(n, dtype=int)
+    for i, j in bl:
+        deg[i] += 1
+        deg[j] += 1
+    rot = [(i, j) for i, j in bl if Z[i] > 1 and Z[j] > 1 and deg[i] > 1 and deg[j] > 1]
+    sides = [_side(n, bl, i, j) for i, j in rot]
+    out = [(Z.copy(), xyz0.copy())]
+    for k in range(1, n_conf):
+        rng = _rng(seed + 0xC0F, index * 65536 + k)
+        x = xyz0.copy()
+        for (i, j), side in zip(rot, sides):
+            # a new torsion for this bond, keeping the old one when every
+            # try collides with the rest of the molecule
+            for _ in range(max_tries // 10):
+                ang = rng.uniform(0.0, 2 * math.pi)
+                y = x.copy()
+                axis = y[j] - y[i]
+                for a in side:
+                    y[a] = y[j] + _rotate(y[a] - y[j], axis, ang)
+                if _min_dist(y) >= 0.9 and bonds(Z, y) == bl:
+                    x = y
+                    break
+        for _ in range(max_tries):
+            y = x.copy()
+            for a in range(n):
+                for c in range(3):
+                    y[a, c] += rng.uniform(-jitter, jitter)
+            if _min_dist(y) >= 0.9 and bonds(Z, y) == bl:
+                out.append((Z.copy(), y))
+                break
+        else:
+            raise RuntimeError("conformers(): no acceptable jitter after %d draws" % max_tries)
     return out
 
 
