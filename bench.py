@@ -124,7 +124,8 @@ def run_path(ks, torch, mols, prec, args, steps, warmup):
         times.append(time.perf_counter() - ts)
         kt = b.kernel_times()
         nq = b.quartets()
-        info = dict(nbf=list(b.nbf), ngrid=list(b.n_grid), quartets=nq)
+        info = dict(nbf=list(b.nbf), ngrid=list(b.n_grid), quartets=nq, n_eri=list(b.n_eri),
+                    n_atoms=[len(z) for z, _ in mols])
         b.close()
         last = (res, kt, info)
     torch.cuda.synchronize()
@@ -268,6 +269,28 @@ def main():
                 frac=achieved / PEAK[dtype], traffic=measured_traffic(args, "mixed" if dtype == "f32" else "fp64"),
                 flops_per_launch=fl / max(1, xc_launches), avg_launch_ms=xc_ms, launches=xc_launches)
 
+    # work rates of the other kernels, from the same live HIP-event timings:
+    # ERIs (once per molecule; the grid runs beside them on a second stream),
+    # J/K against its HBM roofline (the unique integrals streamed once per
+    # active molecule-iteration, FP32 in the mixed path), Becke pairs
+    es = 8 if main_prec == ks.KS_FP64 else 4
+    eri_ms = kt.get("eri", (float("nan"), 1))[0]
+    jk_ms, jk_n = kt.get("jk", (float("nan"), 0))
+    grid_ms = kt.get("grid", (float("nan"), 1))[0]
+    nq, nprim = info["quartets"]
+    jk_bytes = float(sum(e * es * it for e, it in zip(info["n_eri"], niter))) / max(1, jk_n)
+    jk_gbs = jk_bytes / (jk_ms * 1e-3) / 1e9 if jk_n else float("nan")
+    rates = {
+        "eri": dict(bound="valu", unique_shell_quartets_per_s=nq / (eri_ms * 1e-3),
+                    primitive_quartets_per_s=nprim / (eri_ms * 1e-3),
+                    unique_integrals_per_s=float(sum(info["n_eri"])) / (eri_ms * 1e-3), avg_launch_ms=eri_ms),
+        "jk": dict(bound="hbm", achieved=jk_gbs, peak=HBM_PEAK, unit="GB/s", frac=jk_gbs / HBM_PEAK,
+                   bytes_per_launch=jk_bytes, avg_launch_ms=jk_ms, launches=jk_n),
+        "grid": dict(bound="valu", becke_pairs_per_s=float(sum(g * n * (n - 1) / 2 for g, n in
+                                                                 zip(info["ngrid"], info["n_atoms"]))) / (grid_ms * 1e-3),
+                     avg_launch_ms=grid_ms),
+    }
+
     serving = None
     if args.serve_requests > 0:
         serving = serving_leg(ks, args)
@@ -279,7 +302,6 @@ def main():
     if not args.no_cpu_baseline:
         cpu, _ = cpu_baseline(mols, args)
 
-    nq, nprim = info["quartets"]
     total_time_per_step = total / args.steps
     line = {
         "metric": METRIC,
@@ -304,7 +326,7 @@ def main():
                    "precision": "mixed: ERI/JK/XC FP32, Loewdin/eigh/DIIS/energy FP64" if dtype == "f32" else "fp64"},
         "iterations": {"mean": float(np.mean(niter)), "max": int(max(niter))},
         "unconverged": int(sum(s != 1 for s in status)),
-        "eri_quartets_per_s": nq * args.steps / total,
+        "kernel_rates": rates,
         "kernel_ms_avg": {k: v[0] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "fp64": fp64,

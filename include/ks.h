@@ -79,7 +79,11 @@ typedef struct {
     int xc_chunks;          /* work groups per molecule for XC (0 = automatic) */
     int guess;              /* initial density: KS_GUESS_ATOM or KS_GUESS_CORE */
     int xc_points;          /* XC launch shape: grid points per sub-block, 16/32/64 (0 = tuned default) */
-    int xc_waves;           /* XC launch shape: wavefronts per work group, 4 or 8 (0 = tuned default) */
+    int xc_waves;           /* XC launch shape: wavefronts per work group, 4, 8 or 16 (0 = tuned default) */
+    int direct;             /* 1: integral-direct SCF (ERIs recomputed in every J/K build, never stored) */
+    double schwarz_tol;     /* Schwarz screening: stored path, skip quartets with Q_ab Q_cd below it (0 = off);
+                               direct path, skip quartets with Q_ab Q_cd max|dP| below it (0 = 1e-12 FP64,
+                               1e-10 mixed) */
 } ks_options;
 
 /* Initial density.  The paper only says C_1 is initialised (section 3.1).

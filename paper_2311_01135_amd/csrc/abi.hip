@@ -275,6 +275,10 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         set_error("unknown xc or precision option");
         return KS_EINVAL;
     }
+    if ((opt.direct != 0 && opt.direct != 1) || !(opt.schwarz_tol >= 0.0)) {
+        set_error("direct must be 0 or 1 and schwarz_tol >= 0");
+        return KS_EINVAL;
+    }
     if (opt.guess != KS_GUESS_ATOM && opt.guess != KS_GUESS_CORE) {
         set_error("unknown guess option %d", opt.guess);
         return KS_EINVAL;
@@ -491,6 +495,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         if ((st = upload(b, &b->d_pair_ao[c], pao))) return st;
         if ((st = upload(b, &b->d_pairs[c], pairs[c]))) return st;
         if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair * 5))) return st;
+        if ((st = dev_alloc(b, &b->d_Q[c], pairs[c].size()))) return st;
     }
     for (int c = 0; c < kNClass; c++)
         if ((st = upload(b, &b->d_qoff[c], qprefix[c]))) return st;
@@ -606,6 +611,13 @@ ks_status eri_build(ks_batch* b)
     if (b->eri_done) return KS_OK;
     ks_status st;
     if (!b->setup_done && (st = ks_setup(b))) return st;
+    if (b->opt.direct || b->opt.schwarz_tol > 0.0) {
+        if ((st = launch_schwarz(b))) return st;
+    }
+    if (b->opt.direct) {        // integral-direct: nothing is stored
+        b->eri_done = true;
+        return KS_OK;
+    }
     const size_t es = b->opt.prec == KS_MIXED ? sizeof(float) : sizeof(double);
     for (int c = 0; c < kNClass; c++) {
         unsigned char* p;
@@ -697,8 +709,8 @@ ks_status step_launch(ks_batch* b)
 {
     ks_status st;
     if (!b->eri_done && (st = eri_build(b))) return st;
-    // mixed path: incremental J/K from P - Pprev (FP32 digest, FP64 accumulation)
-    const bool inc = b->opt.prec == KS_MIXED;
+    // mixed and integral-direct paths: incremental J/K from P - Pprev
+    const bool inc = b->opt.prec == KS_MIXED || b->opt.direct;
     if ((st = launch_jk(b, b->d_P, b->d_J, b->d_K, true, inc, true))) return st;
     if (b->opt.xc != KS_XC_HF && (st = launch_xc(b, b->d_P, b->d_Vxc, true))) return st;
     if ((st = launch_fock(b, b->d_P, b->d_J, b->d_K, b->d_Vxc, b->d_F, true, nullptr))) return st;
@@ -821,6 +833,10 @@ ks_status ks_get_eri(const ks_batch* b, int mol, double* out)
     }
     if (!b->eri_done) {
         set_error("ks_get_eri before eri_build");
+        return KS_ESTATE;
+    }
+    if (b->opt.direct) {
+        set_error("ks_get_eri: an integral-direct batch stores no integrals");
         return KS_ESTATE;
     }
     long neri;

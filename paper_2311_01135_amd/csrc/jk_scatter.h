@@ -1,0 +1,110 @@
+// Scatter of one unique shell quartet's integrals into the J/K accumulators
+// of a work group (LDS), shared by the stored-integral digestion and the
+// integral-direct build.  For a unique shell quartet Q with stabiliser size s
+// (f = 1/s), per component
+//   AJ[ab] += 2 f I P_cd,  AJ[cd] += 2 f I P_ab,
+//   AK[ac] += f I P_bd,  AK[bc] += f I P_ad,  AK[ad] += f I P_bc,  AK[bd] += f I P_ac,
+// and J = AJ + AJ^T, K = AK + AK^T once the work groups are summed.
+#pragma once
+
+#include "ks_internal.h"
+
+namespace ks {
+
+template <typename A>
+__device__ __forceinline__ void lds_add(A* p, A v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// I: the quartet's NA NB NC ND components (a slowest); oa..od: first AO of
+// each shell; bra_key: identifies the bra pair (lanes of a wavefront that
+// all share it sum their J_ab contributions before a single LDS atomic).
+template <int NA, int NB, int NC, int ND, typename A>
+__device__ __forceinline__ void jk_scatter(const A (&I)[NA * NB * NC * ND], int oa, int ob, int oc, int od, A f,
+                                           int bra_key, int N, const A* __restrict__ Ps, A* AJ, A* AK)
+{
+    const int i = bra_key;
+    A pab[NA][NB], pcd[NC][ND], pbd[NB][ND], pbc[NB][NC], pad[NA][ND], pac[NA][NC];
+#pragma unroll
+    for (int a = 0; a < NA; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) pab[a][b] = Ps[(oa + a) * N + ob + b];
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+        for (int d = 0; d < ND; d++) pcd[c][d] = Ps[(oc + c) * N + od + d];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+#pragma unroll
+        for (int d = 0; d < ND; d++) pbd[b][d] = Ps[(ob + b) * N + od + d];
+#pragma unroll
+        for (int c = 0; c < NC; c++) pbc[b][c] = Ps[(ob + b) * N + oc + c];
+    }
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+#pragma unroll
+        for (int d = 0; d < ND; d++) pad[a][d] = Ps[(oa + a) * N + od + d];
+#pragma unroll
+        for (int c = 0; c < NC; c++) pac[a][c] = Ps[(oa + a) * N + oc + c];
+    }
+    A jab[NA][NB] = {}, jcd[NC][ND] = {}, kac[NA][NC] = {}, kbc[NB][NC] = {}, kad[NA][ND] = {}, kbd[NB][ND] = {};
+#pragma unroll
+    for (int a = 0; a < NA; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int d = 0; d < ND; d++) {
+                    const A v = I[((a * NB + b) * NC + c) * ND + d];
+                    jab[a][b] += v * pcd[c][d];
+                    jcd[c][d] += v * pab[a][b];
+                    kac[a][c] += v * pbd[b][d];
+                    kbc[b][c] += v * pad[a][d];
+                    kad[a][d] += v * pbc[b][c];
+                    kbd[b][d] += v * pac[a][c];
+                }
+    const A f2 = A(2) * f;
+    // J_ab: the lanes of a wave usually share the bra pair; then the wave
+    // sums its contributions and one lane adds them (same-address LDS
+    // atomics would serialise)
+    const unsigned long long act = __ballot(1);
+    const unsigned long long same = __ballot(__builtin_amdgcn_readfirstlane(i) == i);
+    if (act == ~0ull && same == act) {
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                A v = f2 * jab[a][b];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                if ((threadIdx.x & 63) == 0) lds_add(&AJ[(oa + a) * N + ob + b], v);
+            }
+    } else {
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[a][b]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+        for (int d = 0; d < ND; d++) lds_add(&AJ[(oc + c) * N + od + d], f2 * jcd[c][d]);
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+#pragma unroll
+        for (int c = 0; c < NC; c++) lds_add(&AK[(oa + a) * N + oc + c], f * kac[a][c]);
+#pragma unroll
+        for (int d = 0; d < ND; d++) lds_add(&AK[(oa + a) * N + od + d], f * kad[a][d]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+#pragma unroll
+        for (int c = 0; c < NC; c++) lds_add(&AK[(ob + b) * N + oc + c], f * kbc[b][c]);
+#pragma unroll
+        for (int d = 0; d < ND; d++) lds_add(&AK[(ob + b) * N + od + d], f * kbd[b][d]);
+    }
+}
+
+}  // namespace ks

@@ -11,6 +11,7 @@
 #include <cmath>
 
 #include "kernels.h"
+#include "jk_scatter.h"
 
 namespace ks {
 
@@ -281,6 +282,9 @@ struct EriArgs {
     const void* tab;
     void* out;              // [ncomp][nq]
     double cut;             // primitive quartets with |prefactor| below this are skipped
+    const double* Qb;       // Schwarz factors of the bra / ket pair class (when schwarz > 0)
+    const double* Qk;
+    double schwarz;         // quartets with Q_ab Q_cd below this are stored as 0 (0 = off)
 };
 
 template <int LA, int LB, int LC, int LD, typename R, typename S>
@@ -296,12 +300,17 @@ __global__ __launch_bounds__(128) void eri_class_kernel(EriArgs g)
     int i, j;
     decode_quartet(C, q, md.npair[class_ket(C)], i, j);
     const int ib = md.pair0[class_bra(C)] + i, ik = md.pair0[class_ket(C)] + j;
+    S* out = (S*)g.out;
+    if (g.schwarz > 0.0 && g.Qb[ib] * g.Qk[ik] < g.schwarz) {
+#pragma unroll
+        for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = S(0);
+        return;
+    }
     const Pair P1 = g.pb[ib], P2 = g.pk[ik];
     const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
     R acc[NCOMP];
     const PairView vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
     eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, (const R*)g.tab, R(g.cut), acc);
-    S* out = (S*)g.out;
 #pragma unroll
     for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
 }
@@ -445,6 +454,140 @@ __global__ void eri_unpack_kernel(const MolDesc* __restrict__ mols, int m, int c
 }
 
 // ---------------------------------------------------------------------------
+// Schwarz factors: Q_ab = max over the components (a_i b_j) of
+// sqrt|(a_i b_j | a_i b_j)|, so |(ab|cd)| <= Q_ab Q_cd for every component.
+// One thread per shell pair of the class; L: angular momenta of the pair.
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__global__ void schwarz_kernel(const Shell* __restrict__ shells, const Pair* __restrict__ pairs,
+                               const double* __restrict__ pp, long npair, const double* __restrict__ tab,
+                               double* __restrict__ Q)
+{
+    constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NAB = NA * NB;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npair) return;
+    const Pair pr = pairs[i];
+    const Shell sa = shells[pr.sa], sb = shells[pr.sb];
+    const PairView v{pp, npair, (int)i};
+    double I[NAB * NAB];
+    eri_quartet<LA, LB, LA, LB, double>(sa, sb, sa, sb, v, v, tab, 0.0, I);
+    double m = 0.0;
+#pragma unroll
+    for (int u = 0; u < NAB; u++) m = fmax(m, fabs(I[u * NAB + u]));
+    Q[i] = sqrt(m);
+}
+
+// ---------------------------------------------------------------------------
+// Integral-direct J/K (the paper's recomputation remedy for the memory of
+// stored integrals, section 5): one work group per (molecule, chunk of its
+// quartets), the density (or its change since the last build) and the J/K
+// accumulators in LDS.  A quartet is skipped when Q_ab Q_cd max|P| < tol;
+// the others are evaluated in FP64 (McMurchie-Davidson, as eri_class_kernel)
+// and scattered with jk_scatter.  Partials go to the J/K partial buffer and
+// are summed by jk_reduce.
+// ---------------------------------------------------------------------------
+struct DirectArgs {
+    const MolDesc* mol;
+    const MolState* state;
+    const JkItem* items;
+    const Shell* shells;
+    const Pair* pairs[3];
+    const int2* pao[3];
+    const double* pp[3];
+    long npp[3];
+    const double* Q[3];
+    const double* tab;
+    const double* P;
+    const double* Pref;     // incremental build: digest P - Pref
+    void* part;
+    long part_stride;
+    double tol;             // density-weighted Schwarz threshold
+    double cut;             // primitive prefactor cut
+    int only_active;
+};
+
+constexpr int kDirectThreads = 256;
+
+template <int LA, int LB, int LC, int LD, typename A>
+__device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc& md, int chunk, int nchunk, double pmax,
+                                             const A* __restrict__ Ps, A* AJ, A* AK)
+{
+    constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
+    constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
+    constexpr int NCOMP = NA * NB * NC * ND;
+    const int N = md.nbf;
+    const long nq = md.nq[C];
+    const long lo = nq * chunk / nchunk, hi = nq * (chunk + 1) / nchunk;
+    const int cb = class_bra(C), ck = class_ket(C);
+    const int nket = md.npair[ck];
+    const double* __restrict__ Qb = g.Q[cb] + md.pair0[cb];
+    const double* __restrict__ Qk = g.Q[ck] + md.pair0[ck];
+    const double qtol = pmax > 0.0 ? g.tol / pmax : 1e300;
+    for (long q = lo + threadIdx.x; q < hi; q += blockDim.x) {
+        int i, j;
+        decode_quartet(C, q, nket, i, j);
+        if (Qb[i] * Qk[j] < qtol) continue;
+        const int ib = md.pair0[cb] + i, ik = md.pair0[ck] + j;
+        const Pair P1 = g.pairs[cb][ib], P2 = g.pairs[ck][ik];
+        const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
+        const PairView vb{g.pp[cb], g.npp[cb], ib}, vk{g.pp[ck], g.npp[ck], ik};
+        double I[NCOMP];
+        eri_quartet<LA, LB, LC, LD, double>(sa, sb, sc, sd, vb, vk, g.tab, g.cut, I);
+        A Ia[NCOMP];
+#pragma unroll
+        for (int k = 0; k < NCOMP; k++) Ia[k] = A(I[k]);
+        const int2 A1 = g.pao[cb][ib], A2 = g.pao[ck][ik];
+        A f = A(1);
+        if (A1.x >> 16) f *= A(0.5);
+        if (A2.x >> 16) f *= A(0.5);
+        if (class_tri(C) && i == j) f *= A(0.5);
+        jk_scatter<NA, NB, NC, ND, A>(Ia, A1.x & 0xffff, A1.y, A2.x & 0xffff, A2.y, f, i, N, Ps, AJ, AK);
+    }
+}
+
+template <typename A>
+__global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
+{
+    const JkItem it = g.items[blockIdx.x];
+    if (g.only_active && g.state[it.mol].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = g.mol[it.mol];
+    const int N = md.nbf, NN = N * N;
+    extern __shared__ __align__(16) unsigned char smem_direct[];
+    A* Ps = (A*)smem_direct;
+    A* AJ = Ps + NN;
+    A* AK = AJ + NN;
+    __shared__ double red[kDirectThreads / 64];
+    const double* P = g.P + md.mat0;
+    const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        const double v = Pr ? P[i] - Pr[i] : P[i];
+        mx = fmax(mx, fabs(v));
+        Ps[i] = A(v);
+        AJ[i] = A(0);
+        AK[i] = A(0);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    double pmax = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) pmax = fmax(pmax, red[w]);
+    direct_class<0, 0, 0, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
+    direct_class<1, 0, 0, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
+    direct_class<1, 0, 1, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
+    direct_class<1, 1, 0, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
+    direct_class<1, 1, 1, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
+    direct_class<1, 1, 1, 1, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
+    __syncthreads();
+    A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        out[i] = AJ[i];
+        out[g.part_stride + i] = AK[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 ks_status launch_int1e(ks_batch* b)
@@ -490,6 +633,9 @@ static ks_status launch_class(ks_batch* b, int c)
     g.tab = std::is_same<R, double>::value ? (const void*)b->d_boys : (const void*)b->d_boys_f;
     g.cut = b->opt.prec == KS_MIXED ? kEriCutMixed : kEriCutFp64;
     g.out = b->d_eri[c];
+    g.Qb = b->d_Q[class_bra(c)];
+    g.Qk = b->d_Q[class_ket(c)];
+    g.schwarz = b->schwarz_done ? b->opt.schwarz_tol : 0.0;
     const long nb = (g.nq + 127) / 128;
     hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S>), dim3((unsigned)nb), dim3(128), 0, b->stream, g);
     KS_HIP(hipGetLastError());
@@ -533,6 +679,76 @@ ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out)
         KS_HIP(hipGetLastError());
     }
     return KS_OK;
+}
+
+template <int LA, int LB>
+static ks_status launch_schwarz_class(ks_batch* b, int c)
+{
+    const long n = b->npairs[c];
+    if (!n) return KS_OK;
+    hipLaunchKernelGGL((schwarz_kernel<LA, LB>), dim3((unsigned)((n + 127) / 128)), dim3(128), 0, b->stream,
+                       b->d_shells, b->d_pairs[c], b->d_pp[c], n, b->d_boys, b->d_Q[c]);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+ks_status launch_schwarz(ks_batch* b)
+{
+    KTimer tm(b, "schwarz");
+    ks_status st;
+    if ((st = launch_schwarz_class<0, 0>(b, 0))) return st;
+    if ((st = launch_schwarz_class<1, 0>(b, 1))) return st;
+    if ((st = launch_schwarz_class<1, 1>(b, 2))) return st;
+    b->schwarz_done = true;
+    return KS_OK;
+}
+
+template <typename A>
+static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, bool incremental)
+{
+    DirectArgs g;
+    g.mol = b->d_mol;
+    g.state = b->d_state;
+    g.items = b->d_jk_items;
+    g.shells = b->d_shells;
+    for (int c = 0; c < 3; c++) {
+        g.pairs[c] = b->d_pairs[c];
+        g.pao[c] = b->d_pair_ao[c];
+        g.pp[c] = b->d_pp[c];
+        g.npp[c] = b->npairs[c];
+        g.Q[c] = b->d_Q[c];
+    }
+    g.tab = b->d_boys;
+    g.P = P;
+    g.Pref = incremental ? b->d_Pprev : nullptr;
+    g.part = b->d_jk_part;
+    g.part_stride = (long)b->max_np * b->max_np;
+    g.tol = b->opt.schwarz_tol > 0.0 ? b->opt.schwarz_tol : (b->opt.prec == KS_MIXED ? 1e-10 : 1e-12);
+    g.cut = b->opt.prec == KS_MIXED ? kEriCutMixed : kEriCutFp64;
+    g.only_active = only_active;
+    int maxn = 0;
+    for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
+    const size_t lds = 3 * (size_t)maxn * maxn * sizeof(A);
+    KS_HIP(hipFuncSetAttribute((const void*)direct_jk_kernel<A>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    KTimer tm(b, "jk_direct");
+    hipLaunchKernelGGL((direct_jk_kernel<A>), dim3((unsigned)b->jk_items.size()), dim3(kDirectThreads), lds, b->stream,
+                       g);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+ks_status launch_direct_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
+                           bool track)
+{
+    if (!b->schwarz_done) {
+        ks_status st = launch_schwarz(b);
+        if (st) return st;
+    }
+    const bool f64 = jk_acc_fp64(b);
+    ks_status st = f64 ? run_direct_jk<double>(b, P, only_active, incremental)
+                       : run_direct_jk<float>(b, P, only_active, incremental);
+    if (st) return st;
+    return launch_jk_reduce(b, f64, P, J, K, only_active, incremental, track);
 }
 
 }  // namespace ks

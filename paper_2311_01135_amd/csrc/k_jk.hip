@@ -17,6 +17,9 @@
 // contraction is a matrix-vector product with no reuse dimension, so it runs
 // on VALU FMAs, bounded by the HBM stream of the integrals.
 #include "kernels.h"
+#include "jk_scatter.h"
+
+#include <type_traits>
 
 namespace ks {
 
@@ -52,11 +55,6 @@ struct JkArgs {
 // fills a CU, and the waves hide the latency of the integral stream.
 constexpr int kJkThreads = 512;
 
-template <typename A>
-__device__ __forceinline__ void lds_add(A* p, A v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
 template <int LA, int LB, int LC, int LD, typename S, typename A>
 __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md, int chunk, int nchunk,
@@ -95,86 +93,7 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
         A I[NCOMP];
 #pragma unroll
         for (int k = 0; k < NCOMP; k++) I[k] = A(eri[(size_t)k * NQ + qg]);
-        A pab[NA][NB], pcd[NC][ND], pbd[NB][ND], pbc[NB][NC], pad[NA][ND], pac[NA][NC];
-#pragma unroll
-        for (int a = 0; a < NA; a++)
-#pragma unroll
-            for (int b = 0; b < NB; b++) pab[a][b] = Ps[(oa + a) * N + ob + b];
-#pragma unroll
-        for (int c = 0; c < NC; c++)
-#pragma unroll
-            for (int d = 0; d < ND; d++) pcd[c][d] = Ps[(oc + c) * N + od + d];
-#pragma unroll
-        for (int b = 0; b < NB; b++) {
-#pragma unroll
-            for (int d = 0; d < ND; d++) pbd[b][d] = Ps[(ob + b) * N + od + d];
-#pragma unroll
-            for (int c = 0; c < NC; c++) pbc[b][c] = Ps[(ob + b) * N + oc + c];
-        }
-#pragma unroll
-        for (int a = 0; a < NA; a++) {
-#pragma unroll
-            for (int d = 0; d < ND; d++) pad[a][d] = Ps[(oa + a) * N + od + d];
-#pragma unroll
-            for (int c = 0; c < NC; c++) pac[a][c] = Ps[(oa + a) * N + oc + c];
-        }
-        A jab[NA][NB] = {}, jcd[NC][ND] = {}, kac[NA][NC] = {}, kbc[NB][NC] = {}, kad[NA][ND] = {}, kbd[NB][ND] = {};
-#pragma unroll
-        for (int a = 0; a < NA; a++)
-#pragma unroll
-            for (int b = 0; b < NB; b++)
-#pragma unroll
-                for (int c = 0; c < NC; c++)
-#pragma unroll
-                    for (int d = 0; d < ND; d++) {
-                        const A v = I[((a * NB + b) * NC + c) * ND + d];
-                        jab[a][b] += v * pcd[c][d];
-                        jcd[c][d] += v * pab[a][b];
-                        kac[a][c] += v * pbd[b][d];
-                        kbc[b][c] += v * pad[a][d];
-                        kad[a][d] += v * pbc[b][c];
-                        kbd[b][d] += v * pac[a][c];
-                    }
-        const A f2 = A(2) * f;
-        // J_ab: the lanes of a wave usually share the bra pair; then the wave
-        // sums its contributions and one lane adds them (same-address LDS
-        // atomics would serialise)
-        const unsigned long long act = __ballot(1);
-        const unsigned long long same = __ballot(__builtin_amdgcn_readfirstlane(i) == i);
-        if (act == ~0ull && same == act) {
-#pragma unroll
-            for (int a = 0; a < NA; a++)
-#pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    A v = f2 * jab[a][b];
-#pragma unroll
-                    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-                    if ((threadIdx.x & 63) == 0) lds_add(&AJ[(oa + a) * N + ob + b], v);
-                }
-        } else {
-#pragma unroll
-            for (int a = 0; a < NA; a++)
-#pragma unroll
-                for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[a][b]);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; c++)
-#pragma unroll
-            for (int d = 0; d < ND; d++) lds_add(&AJ[(oc + c) * N + od + d], f2 * jcd[c][d]);
-#pragma unroll
-        for (int a = 0; a < NA; a++) {
-#pragma unroll
-            for (int c = 0; c < NC; c++) lds_add(&AK[(oa + a) * N + oc + c], f * kac[a][c]);
-#pragma unroll
-            for (int d = 0; d < ND; d++) lds_add(&AK[(oa + a) * N + od + d], f * kad[a][d]);
-        }
-#pragma unroll
-        for (int b = 0; b < NB; b++) {
-#pragma unroll
-            for (int c = 0; c < NC; c++) lds_add(&AK[(ob + b) * N + oc + c], f * kbc[b][c]);
-#pragma unroll
-            for (int d = 0; d < ND; d++) lds_add(&AK[(ob + b) * N + od + d], f * kbd[b][d]);
-        }
+        jk_scatter<NA, NB, NC, ND, A>(I, oa, ob, oc, od, f, i, N, Ps, AJ, AK);
         i = i2;
         j = j2;
     }
@@ -291,20 +210,35 @@ static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool
         hipLaunchKernelGGL((jk_kernel<S, A>), dim3((unsigned)b->jk_items.size()), dim3(kJkThreads), lds, b->stream, g);
     }
     KS_HIP(hipGetLastError());
+    return launch_jk_reduce(b, std::is_same<A, double>::value, P, J, K, only_active, incremental, track);
+}
+
+template <typename A>
+static ks_status run_jk_reduce(ks_batch* b, const double* P, double* J, double* K, bool only_active,
+                               bool incremental, bool track)
+{
     KTimer tr(b, "jk_reduce");
     const int nchunk = b->jk_items.empty() ? 1 : b->jk_items[0].nchunk;
     int maxnn = 0;
     for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
     hipLaunchKernelGGL(jk_reduce_kernel<A>, dim3((maxnn + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
-                       b->d_state, nchunk, (const A*)b->d_jk_part, g.part_stride, (int)only_active, (int)incremental,
-                       track ? P : nullptr, b->d_Pprev, J, K);
+                       b->d_state, nchunk, (const A*)b->d_jk_part, (long)b->max_np * b->max_np, (int)only_active,
+                       (int)incremental, track ? P : nullptr, b->d_Pprev, J, K);
     KS_HIP(hipGetLastError());
     return KS_OK;
+}
+
+ks_status launch_jk_reduce(ks_batch* b, bool acc_fp64, const double* P, double* J, double* K, bool only_active,
+                           bool incremental, bool track)
+{
+    if (acc_fp64) return run_jk_reduce<double>(b, P, J, K, only_active, incremental, track);
+    return run_jk_reduce<float>(b, P, J, K, only_active, incremental, track);
 }
 
 ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
                     bool track)
 {
+    if (b->opt.direct) return launch_direct_jk(b, P, J, K, only_active, incremental, track);
     if (b->opt.prec == KS_MIXED && jk_acc_fp64(b)) return run_jk<float, double>(b, P, J, K, only_active, incremental, track);
     if (b->opt.prec == KS_MIXED) return run_jk<float, float>(b, P, J, K, only_active, incremental, track);
     return run_jk<double, double>(b, P, J, K, only_active, incremental, track);

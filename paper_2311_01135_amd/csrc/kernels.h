@@ -37,12 +37,21 @@ ks_status launch_int1e(ks_batch* b);
 ks_status launch_pairs(ks_batch* b);
 ks_status launch_eri(ks_batch* b);
 ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out);
+// Schwarz factors Q_ab = max_component sqrt|(ab|ab)| of every shell pair.
+ks_status launch_schwarz(ks_batch* b);
+// Integral-direct J/K: the ERIs of every quartet that survives the
+// density-weighted Schwarz test are computed and digested on the fly.
+ks_status launch_direct_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
+                           bool track);
 
 // J/K (k_jk.hip)
 // incremental: digest P - Pprev and add to J, K; track: afterwards Pprev = P.
 ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
                     bool track);
 size_t jk_lds_bytes(const ks_batch* b);
+// J = sum_chunks (AJ + AJ^T), K likewise, from the per-work-item partials.
+ks_status launch_jk_reduce(ks_batch* b, bool acc_fp64, const double* P, double* J, double* K, bool only_active,
+                           bool incremental, bool track);
 bool jk_acc_fp64(const ks_batch* b);
 
 // grid and XC (k_xc.hip)

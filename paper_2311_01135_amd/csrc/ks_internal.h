@@ -150,6 +150,8 @@ struct ks_batch {
     ks::Pair* d_pairs[3] = {nullptr, nullptr, nullptr};
     int2* d_pair_ao[3] = {nullptr, nullptr, nullptr};  // per pair: (AO of sa | (sa == sb) << 16, AO of sb)
     double* d_pp[3] = {nullptr, nullptr, nullptr};   // [5][9][npair] primitive-pair tables
+    double* d_Q[3] = {nullptr, nullptr, nullptr};    // Schwarz factors max sqrt|(ab|ab)| per pair
+    bool schwarz_done = false;
     long* d_qoff[ks::kNClass] = {};  // prefix over molecules (n_mol + 1)
     void* d_eri[ks::kNClass] = {};   // component-major, FP64 or FP32
     double* d_boys = nullptr;

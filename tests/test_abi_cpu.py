@@ -70,6 +70,10 @@ def test_rejects_bad_options(lib):
     assert st == -1 and "diis_space" in err
     st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], prec=7)
     assert st == -1
+    st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], direct=2)
+    assert st == -1 and "direct" in err
+    st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], schwarz_tol=-1.0)
+    assert st == -1 and "schwarz_tol" in err
 
 
 def test_rejects_too_large_fp64(lib):
