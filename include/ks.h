@@ -109,7 +109,10 @@ typedef struct ks_batch ks_batch;
  * Errors: KS_EINVAL for an odd electron count, an element outside
  * {H, C, N, O, F}, non-finite coordinates or atoms closer than 0.1 bohr;
  * KS_EUNSUPPORTED for a molecule with more than 82 basis functions in
- * KS_FP64 (96 in KS_MIXED): the J/K digest keeps 3 N^2 values in 160 KB LDS;
+ * KS_FP64 or 224 in KS_MIXED (up to 96 the per-molecule matrices of every
+ * kernel sit in LDS; larger mixed-path molecules use global-memory J/K
+ * accumulation, an L2-resident density in XC and a global-memory
+ * eigensolver, at lower speed);
  * KS_ENOMEM / KS_EDEVICE for allocation or runtime failures.  On error *out
  * is NULL and nothing is leaked. */
 ks_status ks_batch_create(const ks_options* opt, int n_mol, const int* n_atoms, const int* Z,

@@ -499,6 +499,7 @@ struct DirectArgs {
     const double* tab;
     const double* P;
     const double* Pref;     // incremental build: digest P - Pref
+    const double* dP;       // global mode: the digested density (materialised)
     void* part;
     long part_stride;
     double tol;             // density-weighted Schwarz threshold
@@ -545,7 +546,9 @@ __device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc&
     }
 }
 
-template <typename A>
+// GLOBAL: molecules whose accumulators exceed the LDS; the density comes
+// from dP and the scatter goes to this item's global partial matrices.
+template <typename A, bool GLOBAL>
 __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
 {
     const JkItem it = g.items[blockIdx.x];
@@ -553,9 +556,17 @@ __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
     const MolDesc md = g.mol[it.mol];
     const int N = md.nbf, NN = N * N;
     extern __shared__ __align__(16) unsigned char smem_direct[];
-    A* Ps = (A*)smem_direct;
-    A* AJ = Ps + NN;
-    A* AK = AJ + NN;
+    A *Pl, *AJ, *AK;
+    if constexpr (GLOBAL) {
+        Pl = (A*)(g.dP + md.mat0);
+        AJ = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+        AK = AJ + g.part_stride;
+    } else {
+        Pl = (A*)smem_direct;
+        AJ = Pl + NN;
+        AK = AJ + NN;
+    }
+    const A* Ps = Pl;
     __shared__ double red[kDirectThreads / 64];
     const double* P = g.P + md.mat0;
     const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
@@ -563,7 +574,7 @@ __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
         const double v = Pr ? P[i] - Pr[i] : P[i];
         mx = fmax(mx, fabs(v));
-        Ps[i] = A(v);
+        if constexpr (!GLOBAL) Pl[i] = A(v);
         AJ[i] = A(0);
         AK[i] = A(0);
     }
@@ -579,11 +590,13 @@ __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
     direct_class<1, 1, 0, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
     direct_class<1, 1, 1, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
     direct_class<1, 1, 1, 1, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
-    __syncthreads();
-    A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
-    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-        out[i] = AJ[i];
-        out[g.part_stride + i] = AK[i];
+    if constexpr (!GLOBAL) {
+        __syncthreads();
+        A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+            out[i] = AJ[i];
+            out[g.part_stride + i] = AK[i];
+        }
     }
 }
 
@@ -703,7 +716,7 @@ ks_status launch_schwarz(ks_batch* b)
     return KS_OK;
 }
 
-template <typename A>
+template <typename A, bool GLOBAL>
 static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, bool incremental)
 {
     DirectArgs g;
@@ -721,6 +734,11 @@ static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, b
     g.tab = b->d_boys;
     g.P = P;
     g.Pref = incremental ? b->d_Pprev : nullptr;
+    g.dP = b->d_work;
+    if (GLOBAL) {
+        ks_status st = launch_delta(b, P, g.Pref, only_active);
+        if (st) return st;
+    }
     g.part = b->d_jk_part;
     g.part_stride = (long)b->max_np * b->max_np;
     g.tol = b->opt.schwarz_tol > 0.0 ? b->opt.schwarz_tol : (b->opt.prec == KS_MIXED ? 1e-10 : 1e-12);
@@ -728,11 +746,12 @@ static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, b
     g.only_active = only_active;
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
-    const size_t lds = 3 * (size_t)maxn * maxn * sizeof(A);
-    KS_HIP(hipFuncSetAttribute((const void*)direct_jk_kernel<A>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const size_t lds = GLOBAL ? 0 : 3 * (size_t)maxn * maxn * sizeof(A);
+    KS_HIP(hipFuncSetAttribute((const void*)direct_jk_kernel<A, GLOBAL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
     KTimer tm(b, "jk_direct");
-    hipLaunchKernelGGL((direct_jk_kernel<A>), dim3((unsigned)b->jk_items.size()), dim3(kDirectThreads), lds, b->stream,
-                       g);
+    hipLaunchKernelGGL((direct_jk_kernel<A, GLOBAL>), dim3((unsigned)b->jk_items.size()), dim3(kDirectThreads), lds,
+                       b->stream, g);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
@@ -744,9 +763,11 @@ ks_status launch_direct_jk(ks_batch* b, const double* P, double* J, double* K, b
         ks_status st = launch_schwarz(b);
         if (st) return st;
     }
-    const bool f64 = jk_acc_fp64(b);
-    ks_status st = f64 ? run_direct_jk<double>(b, P, only_active, incremental)
-                       : run_direct_jk<float>(b, P, only_active, incremental);
+    const int mode = jk_mode(b);
+    const bool f64 = mode != 1;
+    ks_status st = mode == 0 ? run_direct_jk<double, false>(b, P, only_active, incremental)
+                 : mode == 1 ? run_direct_jk<float, false>(b, P, only_active, incremental)
+                             : run_direct_jk<double, true>(b, P, only_active, incremental);
     if (st) return st;
     return launch_jk_reduce(b, f64, P, J, K, only_active, incremental, track);
 }

@@ -46,6 +46,7 @@ struct JkArgs {
     long nq[kNClass];
     const double* P;
     const double* Pref;     // incremental build: digest P - Pref (NULL: P itself)
+    const double* dP;       // global mode: the digested density, materialised by delta_kernel
     void* part;             // [items][2][np_max^2]
     long part_stride;       // np_max^2
     int only_active;
@@ -99,7 +100,10 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
     }
 }
 
-template <typename S, typename A>
+// GLOBAL (molecules whose 3 N^2 accumulators exceed the LDS): the density
+// is read from dP and the scatter goes to this item's partial matrices in
+// global memory with atomics (A = double).
+template <typename S, typename A, bool GLOBAL>
 __global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
 {
     const JkItem it = g.items[blockIdx.x];
@@ -107,15 +111,28 @@ __global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
     const MolDesc md = g.mol[it.mol];
     const int N = md.nbf, NN = N * N;
     extern __shared__ __align__(16) unsigned char smem_jk[];
-    A* Ps = (A*)smem_jk;
-    A* AJ = Ps + NN;
-    A* AK = AJ + NN;
-    const double* P = g.P + md.mat0;
-    const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
-    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-        Ps[i] = A(Pr ? P[i] - Pr[i] : P[i]);
-        AJ[i] = A(0);
-        AK[i] = A(0);
+    const A* Ps;
+    A *AJ, *AK;
+    if constexpr (GLOBAL) {
+        Ps = (const A*)(g.dP + md.mat0);
+        AJ = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+        AK = AJ + g.part_stride;
+        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+            AJ[i] = A(0);
+            AK[i] = A(0);
+        }
+    } else {
+        A* Pl = (A*)smem_jk;
+        AJ = Pl + NN;
+        AK = AJ + NN;
+        const double* P = g.P + md.mat0;
+        const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
+        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+            Pl[i] = A(Pr ? P[i] - Pr[i] : P[i]);
+            AJ[i] = A(0);
+            AK[i] = A(0);
+        }
+        Ps = Pl;
     }
     __syncthreads();
     digest_class<0, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
@@ -124,12 +141,26 @@ __global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
     digest_class<1, 1, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
     digest_class<1, 1, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
     digest_class<1, 1, 1, 1, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
-    __syncthreads();
-    A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
-    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-        out[i] = AJ[i];
-        out[g.part_stride + i] = AK[i];
+    if constexpr (!GLOBAL) {
+        __syncthreads();
+        A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+            out[i] = AJ[i];
+            out[g.part_stride + i] = AK[i];
+        }
     }
+}
+
+// dP = P - Pref (or P) for the global-mode digestion, active molecules only.
+__global__ void delta_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state, int only_active,
+                             const double* __restrict__ P, const double* __restrict__ Pref, double* __restrict__ dP)
+{
+    const int m = blockIdx.y;
+    if (only_active && state[m].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = mols[m];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= md.nbf * md.nbf) return;
+    dP[md.mat0 + t] = Pref ? P[md.mat0 + t] - Pref[md.mat0 + t] : P[md.mat0 + t];
 }
 
 // J = sum_chunks (AJ + AJ^T), K = sum_chunks (AK + AK^T), in FP64; added to
@@ -170,22 +201,40 @@ __global__ void jk_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
 // twice the rate of ds_add_f32 here, so the mixed path stores its ERIs in
 // FP32 (half the HBM stream) but accumulates J/K in FP64; molecules above 82
 // functions fall back to FP32 accumulation.
-bool jk_acc_fp64(const ks_batch* b)
+// 0: LDS, FP64 accumulators; 1: LDS, FP32 (only the mixed path uses it);
+// 2: global partial matrices, FP64.
+int jk_mode(const ks_batch* b)
 {
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
-    return 3 * (size_t)maxn * maxn * sizeof(double) <= 163840;
+    const size_t nn3 = 3 * (size_t)maxn * maxn;
+    if (nn3 * sizeof(double) <= 163840) return 0;
+    if (b->opt.prec == KS_MIXED && nn3 * sizeof(float) <= 163840) return 1;
+    return 2;
 }
+
+bool jk_acc_fp64(const ks_batch* b) { return jk_mode(b) != 1; }
 
 size_t jk_lds_bytes(const ks_batch* b)
 {
-    const size_t es = jk_acc_fp64(b) ? sizeof(double) : sizeof(float);
+    const int mode = jk_mode(b);
+    if (mode == 2) return 0;
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
-    return 3 * (size_t)maxn * maxn * es;
+    return 3 * (size_t)maxn * maxn * (mode == 0 ? sizeof(double) : sizeof(float));
 }
 
-template <typename S, typename A>
+ks_status launch_delta(ks_batch* b, const double* P, const double* Pref, bool only_active)
+{
+    int maxnn = 0;
+    for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
+    hipLaunchKernelGGL(delta_kernel, dim3((maxnn + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
+                       b->d_state, (int)only_active, P, Pref, b->d_work);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+template <typename S, typename A, bool GLOBAL>
 static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
                         bool track)
 {
@@ -200,14 +249,21 @@ static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool
     }
     g.P = P;
     g.Pref = incremental ? b->d_Pprev : nullptr;
+    g.dP = b->d_work;
+    if (GLOBAL) {
+        ks_status st = launch_delta(b, P, g.Pref, only_active);
+        if (st) return st;
+    }
     g.part = b->d_jk_part;
     g.part_stride = (long)b->max_np * b->max_np;
     g.only_active = only_active;
     const size_t lds = jk_lds_bytes(b);
-    KS_HIP(hipFuncSetAttribute((const void*)jk_kernel<S, A>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    KS_HIP(hipFuncSetAttribute((const void*)jk_kernel<S, A, GLOBAL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
     {
         KTimer tm(b, "jk");
-        hipLaunchKernelGGL((jk_kernel<S, A>), dim3((unsigned)b->jk_items.size()), dim3(kJkThreads), lds, b->stream, g);
+        hipLaunchKernelGGL((jk_kernel<S, A, GLOBAL>), dim3((unsigned)b->jk_items.size()), dim3(kJkThreads), lds,
+                           b->stream, g);
     }
     KS_HIP(hipGetLastError());
     return launch_jk_reduce(b, std::is_same<A, double>::value, P, J, K, only_active, incremental, track);
@@ -239,9 +295,14 @@ ks_status launch_jk(ks_batch* b, const double* P, double* J, double* K, bool onl
                     bool track)
 {
     if (b->opt.direct) return launch_direct_jk(b, P, J, K, only_active, incremental, track);
-    if (b->opt.prec == KS_MIXED && jk_acc_fp64(b)) return run_jk<float, double>(b, P, J, K, only_active, incremental, track);
-    if (b->opt.prec == KS_MIXED) return run_jk<float, float>(b, P, J, K, only_active, incremental, track);
-    return run_jk<double, double>(b, P, J, K, only_active, incremental, track);
+    const int mode = jk_mode(b);
+    if (b->opt.prec == KS_MIXED) {
+        if (mode == 0) return run_jk<float, double, false>(b, P, J, K, only_active, incremental, track);
+        if (mode == 1) return run_jk<float, float, false>(b, P, J, K, only_active, incremental, track);
+        return run_jk<float, double, true>(b, P, J, K, only_active, incremental, track);
+    }
+    if (mode == 0) return run_jk<double, double, false>(b, P, J, K, only_active, incremental, track);
+    return run_jk<double, double, true>(b, P, J, K, only_active, incremental, track);
 }
 
 }  // namespace ks

@@ -64,6 +64,16 @@ __device__ double block_max(double v, double* red)
 __device__ void wg_matmul(int N, const double* __restrict__ A, bool ta, const double* __restrict__ B, bool tb,
                           double* C, double* sm)
 {
+    if (!sm) {      // molecules too large for LDS: operands read from global memory (L2)
+        for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
+            const int i = t / N, j = t % N;
+            double s = 0.0;
+            for (int k = 0; k < N; k++) s += (ta ? A[k * N + i] : A[i * N + k]) * (tb ? B[j * N + k] : B[k * N + j]);
+            C[t] = s;
+        }
+        __syncthreads();
+        return;
+    }
     double* As = sm;             // op(A), row-major
     double* Bs = sm + N * N;     // op(B), row-major (+4 doubles of slack for the last column block)
     for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
@@ -105,6 +115,7 @@ struct ScfArgs {
     double *Fp, *C, *eps;
     double *work;           // 3 * nmat
     double *Fh, *Eh;        // diis_space * nmat
+    int lds_mm;             // wg_matmul stages its operands in LDS (0: molecules too large)
     const double* exc;
     long nmat;
     double a0;
@@ -208,15 +219,15 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
     const double *F = g.F + o, *P = g.P + o, *S = g.S + o, *X = g.X + o;
     double *W0 = g.work + o, *W1 = g.work + g.nmat + o, *W2 = g.work + 2 * g.nmat + o;
     const int it = st.iter + 1;
-    wg_matmul(N, F, false, P, false, W0, smem_scf);
-    wg_matmul(N, W0, false, S, false, W1, smem_scf);     // FPS
+    wg_matmul(N, F, false, P, false, W0, g.lds_mm ? smem_scf : nullptr);
+    wg_matmul(N, W0, false, S, false, W1, g.lds_mm ? smem_scf : nullptr);     // FPS
     for (int t = threadIdx.x; t < NN; t += blockDim.x) {
         const int i = t / N, j = t % N;
         W0[t] = W1[i * N + j] - W1[j * N + i];
     }
     __syncthreads();
-    wg_matmul(N, X, true, W0, false, W2, smem_scf);
-    wg_matmul(N, W2, false, X, false, W0, smem_scf);     // e
+    wg_matmul(N, X, true, W0, false, W2, g.lds_mm ? smem_scf : nullptr);
+    wg_matmul(N, W2, false, X, false, W0, g.lds_mm ? smem_scf : nullptr);     // e
     double mx = 0.0;
     for (int t = threadIdx.x; t < NN; t += blockDim.x) mx = fmax(mx, fabs(W0[t]));
     const double err = block_max(mx, red);
@@ -277,8 +288,8 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
         __syncthreads();
         Fsrc = W1;
     }
-    wg_matmul(N, X, true, Fsrc, false, W2, smem_scf);
-    wg_matmul(N, W2, false, X, false, g.Fp + o, smem_scf);
+    wg_matmul(N, X, true, Fsrc, false, W2, g.lds_mm ? smem_scf : nullptr);
+    wg_matmul(N, W2, false, X, false, g.Fp + o, g.lds_mm ? smem_scf : nullptr);
     if (threadIdx.x == 0) {
         st.iter = it;
         st.err = err;
@@ -319,8 +330,8 @@ __global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const doub
     const int m = blockIdx.x;
     const MolDesc md = g.mol[m];
     const long o = md.mat0;
-    wg_matmul(md.nbf, g.X + o, true, A + o, false, g.work + o, smem_scf);
-    wg_matmul(md.nbf, g.work + o, false, g.X + o, false, g.Fp + o, smem_scf);
+    wg_matmul(md.nbf, g.X + o, true, A + o, false, g.work + o, g.lds_mm ? smem_scf : nullptr);
+    wg_matmul(md.nbf, g.work + o, false, g.X + o, false, g.Fp + o, g.lds_mm ? smem_scf : nullptr);
 }
 
 // Symmetric eigenproblem, parallel-order cyclic Jacobi (round-robin pairing:
@@ -337,15 +348,18 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
                                                            const double* __restrict__ src, double* __restrict__ vecs,
                                                            double* __restrict__ vals, const double* __restrict__ warm,
                                                            double* __restrict__ keep, double* __restrict__ tmp,
-                                                           int* __restrict__ have_warm)
+                                                           int* __restrict__ have_warm, double* __restrict__ gws,
+                                                           long nmat)
 {
     const int m = blockIdx.x;
     if (only_active && state[m].status != KS_MOL_ACTIVE) return;
     const MolDesc md = mols[m];
     const int N = md.nbf, NN = N * N;
     extern __shared__ __align__(16) unsigned char smem_eig[];
-    double* A = (double*)smem_eig;
-    double* Vv = A + NN;
+    // matrix and vectors in LDS, or (gws: molecules too large for LDS) in
+    // global memory after the warm-start scratch region
+    double* A = gws ? gws + nmat + md.mat0 : (double*)smem_eig;
+    double* Vv = gws ? gws + 2 * nmat + md.mat0 : A + NN;
     __shared__ int rp[kMaxNbf / 2 + 1], rq[kMaxNbf / 2 + 1];
     __shared__ double rc[kMaxNbf / 2 + 1], rs[kMaxNbf / 2 + 1];
     __shared__ double red[2 * kScfThreads / 64];
@@ -489,11 +503,14 @@ __global__ __launch_bounds__(kScfThreads) void density_kernel(ScfArgs g, int gue
     const int N = md.nbf, no = md.nocc;
     const long o = md.mat0;
     const int fin = guess ? 0 : st.final_;
-    wg_matmul(N, g.X + o, false, g.Fp + o, false, g.C + o, smem_scf);   // Fp holds C' here
+    wg_matmul(N, g.X + o, false, g.Fp + o, false, g.C + o, g.lds_mm ? smem_scf : nullptr);   // Fp holds C' here
     if (!fin) {
-        double* Cs = smem_scf;
-        for (int t = threadIdx.x; t < N * N; t += blockDim.x) Cs[t] = g.C[o + t];
-        __syncthreads();
+        const double* Cs = g.C + o;
+        if (g.lds_mm) {
+            for (int t = threadIdx.x; t < N * N; t += blockDim.x) smem_scf[t] = g.C[o + t];
+            __syncthreads();
+            Cs = smem_scf;
+        }
         for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
             const int i = t / N, j = t % N;
             double s = 0.0;
@@ -521,6 +538,23 @@ __global__ void count_active_kernel(const MolState* __restrict__ state, int n, i
 }
 
 // ---------------------------------------------------------------------------
+static size_t max_nbf(const ks_batch* b)
+{
+    int maxn = 0;
+    for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
+    return (size_t)maxn;
+}
+
+// LDS available to dynamic allocations of the SCF kernels (their static
+// arrays take a few KB)
+constexpr size_t kScfLds = 152 * 1024;
+
+static bool matmul_fits(const ks_batch* b)
+{
+    const size_t n = max_nbf(b);
+    return sizeof(double) * (2 * n * n + 4) <= kScfLds;
+}
+
 static ScfArgs scf_args(ks_batch* b, bool only_active)
 {
     ScfArgs g;
@@ -539,22 +573,27 @@ static ScfArgs scf_args(ks_batch* b, bool only_active)
     g.max_iter = b->opt.max_iter;
     g.diis_space = b->opt.diis_space;
     g.only_active = only_active;
+    g.lds_mm = matmul_fits(b);
     return g;
 }
 
 // dynamic LDS of the kernels that call wg_matmul
 static size_t matmul_lds(const ks_batch* b)
 {
-    int maxn = 0;
-    for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
-    return sizeof(double) * (2 * (size_t)maxn * maxn + 4);
+    const size_t n = max_nbf(b);
+    return matmul_fits(b) ? sizeof(double) * (2 * n * n + 4) : 0;
+}
+
+static bool eigh_fits(const ks_batch* b)
+{
+    const size_t n = max_nbf(b);
+    return 2 * sizeof(double) * n * n <= kScfLds;
 }
 
 static size_t eigh_lds(const ks_batch* b)
 {
-    int maxn = 0;
-    for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
-    return 2 * sizeof(double) * (size_t)maxn * maxn;
+    const size_t n = max_nbf(b);
+    return eigh_fits(b) ? 2 * sizeof(double) * n * n : 0;
 }
 
 // warm == nullptr: cold start from the identity.  Otherwise warm/keep hold the
@@ -566,7 +605,7 @@ static ks_status run_eigh(ks_batch* b, bool only_active, const double* src, doub
     KS_HIP(hipFuncSetAttribute((const void*)eigh_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(eigh_kernel, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, b->d_mol, b->d_state,
                        (int)only_active, src, vecs, vals, (const double*)warm, warm, warm ? b->d_work : nullptr,
-                       warm ? b->d_have_warm : nullptr);
+                       warm ? b->d_have_warm : nullptr, eigh_fits(b) ? nullptr : b->d_work, b->nmat);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }

@@ -301,12 +301,13 @@ struct ShellLds {
 __host__ __device__ constexpr size_t al32(size_t x) { return (x + 31) & ~(size_t)31; }
 __host__ __device__ constexpr int xc_ldp(int np) { return np + 4; }
 __host__ __device__ constexpr int xc_ldg(int bp) { return bp + 4; }
-__host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np, int ns)
+__host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np, int ns,
+                                                      bool pglobal = false)
 {
     return al32((size_t)bp * 4 * sizeof(double)) + al32((size_t)nw * sizeof(double))
            + al32((size_t)ns * 3 * sizeof(double)) + al32((size_t)ns * 6 * es) + al32((size_t)bp * 4 * es)
            + al32((size_t)bp * 9 * es) + al32((size_t)(np / 16) * 4 * bp * es)
-           + al32((size_t)np * xc_ldp(np) * es)
+           + (pglobal ? 0 : al32((size_t)np * xc_ldp(np) * es))
            + al32((size_t)(es == sizeof(float) ? 5 : 4) * np * xc_ldg(bp) * es) + al32((size_t)ns * sizeof(int));
 }
 
@@ -477,7 +478,52 @@ __device__ __forceinline__ void gemm_phit_w_pair(const unsigned int* __restrict_
     }
 }
 
-template <typename T, int BP, int NW, int MAXT>
+// Phi^T W for many tiles per wave (molecules beyond the LDS-resident
+// density): groups of four tiles with compile-time accumulator indices; a
+// group runs when any of its tiles is this wave's, and tiles past the last
+// one repeat tile 0 into accumulators that are never written out.
+template <int NW, int BP, int MAXT>
+__device__ __forceinline__ void gemm_phit_w_pair_grouped(const unsigned int* __restrict__ Phi,
+                                                         const unsigned int* __restrict__ Wt, int LDG, int NT,
+                                                         int nj, int wave, int lane, f4_t (&acc)[MAXT])
+{
+    static_assert(MAXT % 4 == 0, "groups of four tiles");
+    const int l16 = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int g0 = 0; g0 < MAXT; g0 += 4) {
+        if (g0 < nj) {
+            int pa[4], pb[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                int t = wave + (g0 + j) * NW;
+                if (t >= NT * NT) t = 0;
+                pa[j] = ((t / NT) * 16 + l16) * LDG + 4 * q;
+                pb[j] = ((t % NT) * 16 + l16) * LDG + 4 * q;
+            }
+#pragma unroll
+            for (int kk = 0; kk < BP; kk += 16) {
+                u32x4_t a[4], bv[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    a[j] = *(const u32x4_t*)(Phi + pa[j] + kk);
+                    bv[j] = *(const u32x4_t*)(Wt + pb[j] + kk);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    u32x4_t bs;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) bs[i] = pair_swap(bv[j][i]);
+                    acc[g0 + j] = mfma_pair(a[j], bv[j], acc[g0 + j]);
+                    acc[g0 + j] = mfma_pair(a[j], bs, acc[g0 + j]);
+                }
+            }
+        }
+    }
+}
+
+// PGL: the padded density is read from global memory (L2) instead of LDS,
+// for molecules whose density does not fit next to the AO planes.
+template <typename T, int BP, int NW, int MAXT, bool PGL = false>
 __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
 {
     constexpr int NTH = NW * 64;
@@ -491,7 +537,7 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     const int m = it.mol;
     if (g.only_active && g.state[m].status != KS_MOL_ACTIVE) return;
     const MolDesc md = g.mol[m];
-    const int N = md.nbf, NP = md.np, NT = NP >> 4, LDP = xc_ldp(NP), PL = NP * LDG;
+    const int N = md.nbf, NP = md.np, NT = NP >> 4, LDP = PGL ? NP : xc_ldp(NP), PL = NP * LDG;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l16 = lane & 15;
@@ -515,7 +561,7 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     T* fpart = (T*)take(BP * 9 * sizeof(T));                  // [3][BP][3]: e, v_rho, v_sigma per part
     T* rpart = (T*)take((size_t)NT * 4 * BP * sizeof(T));     // [NT][4][BP]
     constexpr bool kPair = sizeof(T) == 4;                    // FP32: Phi and W as bf16 pairs
-    T* Pl = (T*)take((size_t)NP * LDP * sizeof(T));           // [NP][LDP]
+    T* Pl = PGL ? (T*)((const T*)g.Pt + g.ptoff[m]) : (T*)take((size_t)NP * LDP * sizeof(T));   // [NP][LDP]
     T* Phi = (T*)take((size_t)(kPair ? 5 : 4) * PL * sizeof(T));   // 4 (FP32: 5) planes [NP][LDG]
     T* Wt = Phi + PL;                                         // W^T overwrites d/dx Phi
     unsigned int* Php = (unsigned int*)(Phi + 4 * PL);        // FP32: Phi as bf16 pairs
@@ -524,7 +570,8 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     const T* __restrict__ Pt = (const T*)g.Pt + g.ptoff[m];
     const Shell* __restrict__ sh = g.shells + md.shell0;
 
-    for (int i = tid; i < NP * NP; i += NTH) Pl[(i / NP) * LDP + i % NP] = Pt[i];
+    if constexpr (!PGL)
+        for (int i = tid; i < NP * NP; i += NTH) Pl[(i / NP) * LDP + i % NP] = Pt[i];
     for (int i = tid; i < md.nshell; i += NTH) {
         const Shell& S = sh[i];
 #pragma unroll
@@ -689,7 +736,9 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
         // A += Phi^T W   (NP x BP) . (BP x NP), this wave's tiles
         lane_g = lane;
         asm volatile("" : "+v"(lane_g));
-        if constexpr (kPair) {
+        if constexpr (kPair && MAXT > 9) {
+            gemm_phit_w_pair_grouped<NW, BP, MAXT>(Php, (const unsigned int*)Wt, LDG, NT, nj2, wave, lane_g, acc);
+        } else if constexpr (kPair) {
             const unsigned int* Pw = Php;
             const unsigned int* Ww = (const unsigned int*)Wt;
             switch (nj2) {
@@ -795,6 +844,15 @@ XcShape xc_shape(const ks_batch* b)
         const int nw = b->opt.xc_waves > 0 ? b->opt.xc_waves : s.nw;
         if (xc_shape_ok(bp, nw)) { s.bp = bp; s.nw = nw; }
     }
+    if (f32 && b->max_np > 96) {
+        // beyond the LDS-resident density: P from L2, 16-point sub-blocks,
+        // 8 waves (the Phi^T W tiles of up to 224 functions fit their registers)
+        s.bp = 16;
+        s.nw = 8;
+        s.pglobal = true;
+        s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, true);
+        return s;
+    }
     while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell) > kLdsMax) s.bp /= 2;
     s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell);
     return s;
@@ -802,13 +860,13 @@ XcShape xc_shape(const ks_batch* b)
 
 int xc_block_points(const ks_batch* b) { return xc_shape(b).bp; }
 
-template <typename T, int BP, int NW, int MAXT>
+template <typename T, int BP, int NW, int MAXT, bool PGL = false>
 static ks_status launch_xc_shape(ks_batch* b, const XcArgs& g, size_t lds)
 {
-    KS_HIP(hipFuncSetAttribute((const void*)xc_kernel<T, BP, NW, MAXT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
+    KS_HIP(hipFuncSetAttribute((const void*)xc_kernel<T, BP, NW, MAXT, PGL>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer tx(b, "xc");
-    hipLaunchKernelGGL((xc_kernel<T, BP, NW, MAXT>), dim3((unsigned)b->xc_items.size()), dim3(NW * 64), lds,
+    hipLaunchKernelGGL((xc_kernel<T, BP, NW, MAXT, PGL>), dim3((unsigned)b->xc_items.size()), dim3(NW * 64), lds,
                        b->stream, g);
     KS_HIP(hipGetLastError());
     return KS_OK;
@@ -842,7 +900,18 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
     const XcShape s = xc_shape(b);
     const bool big = b->max_np > 80;     // 6 x 6 tiles of 16
     ks_status st;
-    if (s.nw == 16) {
+    if (s.pglobal) {
+        if constexpr (sizeof(T) == 4) {
+            if (b->max_np > 224) {
+                set_error("XC: %d padded basis functions exceed the 224 of the large-molecule kernel", b->max_np);
+                return KS_EUNSUPPORTED;
+            }
+            st = launch_xc_shape<T, 16, 8, 28, true>(b, g, s.lds);
+        } else {
+            set_error("XC: FP64 molecules beyond the LDS-resident density are not supported");
+            return KS_EUNSUPPORTED;
+        }
+    } else if (s.nw == 16) {
         if (s.bp == 64) st = big ? launch_xc_shape<T, 64, 16, 3>(b, g, s.lds) : launch_xc_shape<T, 64, 16, 2>(b, g, s.lds);
         else if (s.bp == 32) st = big ? launch_xc_shape<T, 32, 16, 3>(b, g, s.lds) : launch_xc_shape<T, 32, 16, 2>(b, g, s.lds);
         else st = big ? launch_xc_shape<T, 16, 16, 3>(b, g, s.lds) : launch_xc_shape<T, 16, 16, 2>(b, g, s.lds);

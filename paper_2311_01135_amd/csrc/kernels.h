@@ -53,13 +53,16 @@ size_t jk_lds_bytes(const ks_batch* b);
 ks_status launch_jk_reduce(ks_batch* b, bool acc_fp64, const double* P, double* J, double* K, bool only_active,
                            bool incremental, bool track);
 bool jk_acc_fp64(const ks_batch* b);
+int jk_mode(const ks_batch* b);     // 0 LDS FP64, 1 LDS FP32, 2 global FP64 accumulation
+// dP = P - Pref (or P) into the batch work area, for global-mode digestion
+ks_status launch_delta(ks_batch* b, const double* P, const double* Pref, bool only_active);
 
 // grid and XC (k_xc.hip)
 ks_status launch_grid(ks_batch* b, hipStream_t s);
 ks_status launch_xc(ks_batch* b, const double* P, double* V, bool only_active);
 size_t xc_lds_bytes(const ks_batch* b);
 int xc_block_points(const ks_batch* b);
-struct XcShape { int bp = 32, nw = 8; size_t lds = 0; };
+struct XcShape { int bp = 32, nw = 8; bool pglobal = false; size_t lds = 0; };
 XcShape xc_shape(const ks_batch* b);
 
 // SCF steps (k_scf.hip)

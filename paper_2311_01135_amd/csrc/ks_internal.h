@@ -12,7 +12,12 @@
 
 namespace ks {
 
-constexpr int kMaxNbf = 96;     // largest molecule the LDS-resident kernels take
+// Largest molecule (basis functions) of the mixed path: up to 96 every
+// kernel keeps its per-molecule matrices in LDS; above that J/K accumulate
+// in global memory, XC reads the density from L2 and the eigensolver and
+// the N x N products work in global memory.  The FP64 path stops at 82
+// (its XC accumulators for larger molecules exceed the registers).
+constexpr int kMaxNbf = 224;
 constexpr int kNPrim = 3;       // STO-3G: three primitives per shell
 constexpr int kNPrimPair = kNPrim * kNPrim;
 constexpr int kMaxDiis = 8;
@@ -173,7 +178,7 @@ struct ks_batch {
     // J/K work
     std::vector<ks::JkItem> jk_items;
     ks::JkItem* d_jk_items = nullptr;
-    void* d_jk_part = nullptr;      // [items][2][kMaxNbf^2]
+    void* d_jk_part = nullptr;      // [items][2][max_np^2]
     // XC work
     std::vector<ks::XcItem> xc_items;
     ks::XcItem* d_xc_items = nullptr;

@@ -1,0 +1,100 @@
+"""Molecules beyond the LDS-resident kernels (mixed path, N > 96 functions):
+a batch that holds one 20-heavy-atom molecule (N = 130) runs every kernel in
+its large-molecule mode (global-memory J/K accumulation, XC with the
+density in L2 and grouped tiles, global-memory eigensolver and N x N
+products).  The small molecules of the same batch are checked against the
+oracle (J/K and V_XC from random densities, SCF energies), the large one
+against the oracle SCF result written by tests/golden/make_golden_large.py.
+
+Tolerances (mixed path): J, K, V_XC elements 1e-5; E_XC 1e-5 Ha; SCF
+|dE|, |d gap| <= 1e-4 Ha.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2311_01135_amd import molgen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_scf_large.json")
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_01135_amd import ks as K
+    K.load()
+    return K
+
+
+def _mols():
+    return [molgen.water(0), molgen.tree(3, 7, 3), molgen.tree(20, 4, 0)]
+
+
+def _rand_density(o, seed):
+    rng = np.random.default_rng(seed)
+    S, _, _ = o.int1e()
+    w, U = np.linalg.eigh(S)
+    X = U @ np.diag(w ** -0.5) @ U.T
+    Q, _ = np.linalg.qr(rng.standard_normal((o.nbf, o.nbf)))
+    C = X @ Q[:, :o.nocc]
+    return 2 * C @ C.T
+
+
+@pytest.fixture(scope="module")
+def batch(ks):
+    mols = _mols()
+    b = ks.Batch(mols, prec=ks.KS_MIXED)
+    assert max(b.nbf) > 96
+    b.setup()
+    b.eri_build()
+    yield mols, b
+    b.close()
+
+
+def test_large_batch_kernels_vs_oracle(batch):
+    mols, b = batch
+    orc = [O.Mol(z, x) for z, x in mols[:2]]
+    Ps = [_rand_density(o, 50 + m) for m, o in enumerate(orc)]
+    # the large molecule gets its own random density; only its shape matters here
+    ol = O.Mol(*mols[2])
+    Ps.append(_rand_density(ol, 52))
+    P = b.pack(Ps)
+    J, K, V = b.empty(), b.empty(), b.empty()
+    b.jk_build(P, J, K)
+    exc = b.xc_build(P, V)
+    Js, Ks, Vs = b.unpack(J), b.unpack(K), b.unpack(V)
+    for m, o in enumerate(orc):
+        Jr, Kr = o.jk(o.eri(), Ps[m])
+        er, Vr = o.xc(O.XC_B3LYP, o.grid(), Ps[m])
+        assert np.abs(Js[m] - Jr).max() < 1e-5, m
+        assert np.abs(Ks[m] - Kr).max() < 1e-5, m
+        assert abs(exc[m] - er) < 1e-5, (m, exc[m], er)
+        assert np.abs(Vs[m] - Vr).max() < 1e-5, m
+    for M in (Js[2], Ks[2], Vs[2]):
+        assert np.isfinite(M).all() and np.abs(M - M.T).max() < 1e-9
+
+
+def test_large_batch_scf(ks):
+    mols = _mols()
+    refs = [O.Mol(z, x).scf(xc=O.XC_B3LYP) for z, x in mols[:2]]
+    with ks.Batch(mols, prec=ks.KS_MIXED) as b:
+        b.scf_solve()
+        for m, ref in enumerate(refs):
+            r = b.result(m)
+            assert r["status"] == 1
+            assert abs(r["E"] - ref["E"]) <= 1e-4 and abs(r["gap"] - ref["gap"]) <= 1e-4, m
+        r = b.result(2)
+        assert r["status"] == 1 and r["gap"] > 0
+        if not os.path.exists(GOLD):
+            pytest.skip("no oracle result for the 20-heavy-atom molecule")
+        with open(GOLD) as f:
+            g = [x for x in json.load(f)["molecules"] if x["index"] == 0][0]
+        assert g["nbf"] == b.nbf[2]
+        assert abs(r["E"] - g["E"]) <= 1e-4 and abs(r["gap"] - g["gap"]) <= 1e-4, (r["E"], g["E"])
