@@ -82,19 +82,17 @@ def test_large_batch_kernels_vs_oracle(batch):
 
 
 def test_large_batch_scf(ks):
-    mols = _mols()
+    mols = _mols() + [molgen.tree(20, 4, 1)]
     refs = [O.Mol(z, x).scf(xc=O.XC_B3LYP) for z, x in mols[:2]]
+    with open(GOLD) as f:
+        gold = {x["index"]: x for x in json.load(f)["molecules"]}
     with ks.Batch(mols, prec=ks.KS_MIXED) as b:
         b.scf_solve()
         for m, ref in enumerate(refs):
             r = b.result(m)
             assert r["status"] == 1
             assert abs(r["E"] - ref["E"]) <= 1e-4 and abs(r["gap"] - ref["gap"]) <= 1e-4, m
-        r = b.result(2)
-        assert r["status"] == 1 and r["gap"] > 0
-        if not os.path.exists(GOLD):
-            pytest.skip("no oracle result for the 20-heavy-atom molecule")
-        with open(GOLD) as f:
-            g = [x for x in json.load(f)["molecules"] if x["index"] == 0][0]
-        assert g["nbf"] == b.nbf[2]
-        assert abs(r["E"] - g["E"]) <= 1e-4 and abs(r["gap"] - g["gap"]) <= 1e-4, (r["E"], g["E"])
+        for m, idx in ((2, 0), (3, 1)):
+            r, g = b.result(m), gold[idx]
+            assert r["status"] == 1 and g["nbf"] == b.nbf[m]
+            assert abs(r["E"] - g["E"]) <= 1e-4 and abs(r["gap"] - g["gap"]) <= 1e-4, (idx, r["E"], g["E"])
