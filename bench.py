@@ -1,14 +1,19 @@
 """Throughput benchmark: batched restricted B3LYP/STO-3G SCF solves on one GPU.
 
 A step is one full pass of the hot path over one batch of synthetic molecules
-(9-11 heavy C/N/O/F atoms plus H, the paper's workload size): batch creation
+(default 4096 molecules of 9-11 heavy C/N/O/F atoms plus H, the paper's
+workload size, seed 2): batch creation
 (host prep, uploads), one-electron integrals, Loewdin, grid and Becke
 weights, ERIs, and SCF iterations (J/K, XC, Fock, DIIS, eigensolve, density)
 until every molecule has converged, then the results copied to the host.
 
 The headline value is the mixed-precision path (ERIs, J/K and XC in FP32);
 the plain FP64 GPU path runs on the same inputs for the speed ratio and the
-per-molecule energy/gap differences.  The roofline entry is for the XC
+per-molecule energy/gap differences; for the default workload the first 64
+molecules are also compared with stored oracle results.  The larger
+integral-direct workload runs as
+  --n-mol 64 --heavy 20-30 --seed 4 --direct --schwarz-tol 1e-10 --grid 75,18,36
+The roofline entry is for the XC
 kernel (the dominant one), timed live with HIP events on the batch stream.
 The CPU baseline is the FP64 oracle on a bounded sample of the same workload.
 """
@@ -38,7 +43,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--n-mol", type=int, default=256)
+    p.add_argument("--n-mol", type=int, default=4096)
     p.add_argument("--heavy", type=str, default="9-11", help="n or lo-hi heavy atoms")
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison pass")
@@ -48,6 +53,9 @@ def parse():
     p.add_argument("--jk-chunks", type=int, default=0)
     p.add_argument("--xc-chunks", type=int, default=0)
     p.add_argument("--serve-requests", type=int, default=512, help="serving leg requests (0 = skip)")
+    p.add_argument("--grid", type=str, default="50,12,24", help="radial,theta,phi points per atom")
+    p.add_argument("--direct", action="store_true", help="integral-direct J/K (ERIs recomputed every iteration)")
+    p.add_argument("--schwarz-tol", type=float, default=0.0, help="Schwarz screening threshold (0 = off)")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="run one plain streaming copy of this many MiB before the timed region (the reference "
                         "kernel that scales hardware byte counters)")
@@ -94,6 +102,37 @@ def copy_calibration(torch, mib):
     del src, dst
 
 
+def grid_shape(args):
+    r, t, f = (int(v) for v in args.grid.split(","))
+    return r, t, f
+
+
+def oracle_subset(args, res, res64):
+    """|dE|, |dgap| of the GPU results against stored oracle SCF results for
+    the first molecules of the workload (tests/golden, written by a script
+    that calls only the oracle), when the stored set is this workload's."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        "oracle_scf_seed2_first64.json")
+    if not os.path.exists(path) or args.direct or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    if doc["seed"] != args.seed or tuple(doc["heavy"]) != heavy_range(args.heavy):
+        return None
+    ref = [m for m in doc["molecules"] if m["index"] < len(res)]
+    if not ref:
+        return None
+    out = dict(n=len(ref), source="tests/golden/oracle_scf_seed2_first64.json")
+    for name, rr in (("main", res), ("fp64_gpu", res64)):
+        if rr is None:
+            continue
+        dE = np.array([abs(rr[m["index"]]["E"] - m["E"]) for m in ref])
+        dg = np.array([abs(rr[m["index"]]["gap"] - m["gap"]) for m in ref])
+        out[name] = dict(max_abs_dE=float(dE.max()), max_abs_dgap=float(dg.max()),
+                         per_molecule_dE=[float(v) for v in dE])
+    return out
+
+
 def solve_batch(ks, mols, prec, timing, args):
     from paper_2311_01135_amd import autotune, molgen
     kw = dict(prec=prec)
@@ -102,6 +141,11 @@ def solve_batch(ks, mols, prec, timing, args):
         kw["jk_chunks"] = args.jk_chunks
     if args.xc_chunks:
         kw["xc_chunks"] = args.xc_chunks
+    kw["n_rad"], kw["n_theta"], kw["n_phi"] = grid_shape(args)
+    if args.direct:
+        kw["direct"] = 1
+    if args.schwarz_tol > 0:
+        kw["schwarz_tol"] = args.schwarz_tol
     b = ks.Batch(mols, **kw)
     if timing:
         b.set_timing(True)
@@ -248,6 +292,7 @@ def main():
 
     fp64 = None
     acc = None
+    res64 = None
     if not args.no_fp64 and not args.fp64_only:
         t64, times64, (res64, kt64, _) = run_path(ks, torch, mols, ks.KS_FP64, args, 1, 0)
         dE = np.array([abs(a["E"] - b["E"]) for a, b in zip(res, res64)])
@@ -258,6 +303,12 @@ def main():
                    max_abs_dgap_vs_fp64_gpu=float(dg.max()), n_over_1e4=int(((dE > 1e-4) | (dg > 1e-4)).sum()),
                    fp64_unconverged=int(sum(r["status"] != 1 for r in res64)))
         print("fp64 path: %.2f solves/s; max|dE| %.2e max|dgap| %.2e" % (fp64["value"], dE.max(), dg.max()),
+              file=sys.stderr, flush=True)
+
+    vs_oracle = oracle_subset(args, res, res64)
+    if vs_oracle:
+        print("vs oracle (%d molecules): main max|dE| %.2e max|dgap| %.2e"
+              % (vs_oracle["n"], vs_oracle["main"]["max_abs_dE"], vs_oracle["main"]["max_abs_dgap"]),
               file=sys.stderr, flush=True)
 
     # roofline of the XC kernel (dominant), from the last timed step
@@ -280,12 +331,15 @@ def main():
     nq, nprim = info["quartets"]
     jk_bytes = float(sum(e * es * it for e, it in zip(info["n_eri"], niter))) / max(1, jk_n)
     jk_gbs = jk_bytes / (jk_ms * 1e-3) / 1e9 if jk_n else float("nan")
+    jkd_ms, jkd_n = kt.get("jk_direct", (float("nan"), 0))
     rates = {
         "eri": dict(bound="valu", unique_shell_quartets_per_s=nq / (eri_ms * 1e-3),
                     primitive_quartets_per_s=nprim / (eri_ms * 1e-3),
                     unique_integrals_per_s=float(sum(info["n_eri"])) / (eri_ms * 1e-3), avg_launch_ms=eri_ms),
         "jk": dict(bound="hbm", achieved=jk_gbs, peak=HBM_PEAK, unit="GB/s", frac=jk_gbs / HBM_PEAK,
                    bytes_per_launch=jk_bytes, avg_launch_ms=jk_ms, launches=jk_n),
+        "jk_direct": dict(bound="valu", avg_launch_ms=jkd_ms, launches=jkd_n,
+                          note="integral-direct: ERIs recomputed inside the digestion, nothing streamed") if jkd_n else None,
         "grid": dict(bound="valu", becke_pairs_per_s=float(sum(g * n * (n - 1) / 2 for g, n in
                                                                  zip(info["ngrid"], info["n_atoms"]))) / (grid_ms * 1e-3),
                      avg_launch_ms=grid_ms),
@@ -317,9 +371,12 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "batch of %d synthetic saturated-tree molecules, %s heavy atoms {C,N,O,F}+H, "
-                               "B3LYP/STO-3G, grid 50x12x24 per atom with Becke weights, DIIS(8), "
+                               "B3LYP/STO-3G, grid %s per atom with Becke weights, DIIS(8), "
                                "converged at dE<1e-9 Ha & commutator<1e-7 (FP64) or dE<1e-6 Ha & "
-                               "commutator<1e-5 (mixed)" % (args.n_mol, args.heavy),
+                               "commutator<1e-5 (mixed)%s%s"
+                               % (args.n_mol, args.heavy, "x".join(str(v) for v in grid_shape(args)),
+                                  ", integral-direct J/K" if args.direct else "",
+                                  ", Schwarz screening %g" % args.schwarz_tol if args.schwarz_tol > 0 else ""),
                    "n_mol": args.n_mol, "seed": args.seed,
                    "nbf_range": [min(info["nbf"]), max(info["nbf"])],
                    "grid_points": int(sum(info["ngrid"])),
@@ -331,6 +388,7 @@ def main():
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "fp64": fp64,
         "accuracy": acc,
+        "vs_oracle": vs_oracle,
         "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -57,23 +57,12 @@ __device__ double block_max(double v, double* red)
     return r;
 }
 
-// C = op(A) op(B), N x N, global memory (L2-resident); ends with a barrier.
 // C = op(A) op(B) for N x N row-major matrices: both operands are staged in
 // LDS (sm: 2 N^2 + 4 doubles), each thread forms four adjacent outputs of a
-// row; every output sums over k in ascending order.  C may alias A or B.
-__device__ void wg_matmul(int N, const double* __restrict__ A, bool ta, const double* __restrict__ B, bool tb,
-                          double* C, double* sm)
+// row; every output sums over k in ascending order.  C must not alias A or B.
+__device__ void wg_matmul_full(int N, const double* __restrict__ A, bool ta, const double* __restrict__ B, bool tb,
+                               double* C, double* sm)
 {
-    if (!sm) {      // molecules too large for LDS: operands read from global memory (L2)
-        for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
-            const int i = t / N, j = t % N;
-            double s = 0.0;
-            for (int k = 0; k < N; k++) s += (ta ? A[k * N + i] : A[i * N + k]) * (tb ? B[j * N + k] : B[k * N + j]);
-            C[t] = s;
-        }
-        __syncthreads();
-        return;
-    }
     double* As = sm;             // op(A), row-major
     double* Bs = sm + N * N;     // op(B), row-major (+4 doubles of slack for the last column block)
     for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
@@ -105,7 +94,97 @@ __device__ void wg_matmul(int N, const double* __restrict__ A, bool ta, const do
     __syncthreads();
 }
 
-extern __shared__ __align__(16) double smem_scf[];   // 2 N_max^2 + 4 doubles for wg_matmul
+// Panel product for molecules whose operands do not fit in LDS:
+// C (N x N) = alpha op(A) op(B), op(A) N x K, op(B) K x N, leading dimension N
+// for all three.  C is formed in row blocks of kPanR rows; for each block K is
+// walked in panels of kPanK: the op(A) panel [kPanR][kPanK + 1] and the op(B)
+// panel [kPanK][4 ceil(N/4) + 4] are staged in LDS (global reads coalesced
+// for either transpose) and each thread keeps up to kPanT 4 x 4 output tiles
+// in registers.  Every output sums over k in ascending order.  C must not
+// alias A or B.  Needs blockDim.x * kPanT >= (kPanR / 4) ceil(N / 4).
+constexpr int kPanR = 64, kPanK = 32, kPanT = 4;
+__host__ __device__ constexpr int panel_ldb(int n) { return ((n + 3) / 4) * 4 + 4; }
+__host__ __device__ constexpr size_t panel_lds_doubles(int n) { return kPanR * (kPanK + 1) + kPanK * panel_ldb(n); }
+
+__device__ void wg_matmul_panel(int N, int K, const double* __restrict__ A, bool ta, const double* __restrict__ B,
+                                bool tb, double* C, double* sm, double alpha)
+{
+    const int n4 = (N + 3) / 4, ldb = panel_ldb(N), lda = kPanK + 1;
+    double* As = sm;
+    double* Bs = sm + kPanR * lda;
+    const int ntile = (kPanR / 4) * n4;
+    for (int i0 = 0; i0 < N; i0 += kPanR) {
+        double acc[kPanT][16];
+#pragma unroll
+        for (int s = 0; s < kPanT; s++)
+#pragma unroll
+            for (int e = 0; e < 16; e++) acc[s][e] = 0.0;
+        for (int k0 = 0; k0 < K; k0 += kPanK) {
+            const int kb = min(kPanK, K - k0);
+            for (int t = threadIdx.x; t < kPanR * kPanK; t += blockDim.x) {
+                int r, kk;
+                if (ta) { kk = t / kPanR; r = t % kPanR; }
+                else { r = t / kPanK; kk = t % kPanK; }
+                const int i = i0 + r, k = k0 + kk;
+                double v = 0.0;
+                if (i < N && kk < kb) v = ta ? A[(long)k * N + i] : A[(long)i * N + k];
+                As[r * lda + kk] = v;
+            }
+            for (int t = threadIdx.x; t < kPanK * 4 * n4; t += blockDim.x) {
+                int kk, j;
+                if (tb) { j = t / kPanK; kk = t % kPanK; }
+                else { kk = t / (4 * n4); j = t % (4 * n4); }
+                const int k = k0 + kk;
+                double v = 0.0;
+                if (j < N && kk < kb) v = tb ? B[(long)j * N + k] : B[(long)k * N + j];
+                Bs[kk * ldb + j] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < kPanT; s++) {
+                const int tile = threadIdx.x + s * blockDim.x;
+                if (tile < ntile) {
+                    const double* ar = As + 4 * (tile / n4) * lda;
+                    const double* br = Bs + 4 * (tile % n4);
+                    for (int kk = 0; kk < kb; kk++) {
+                        const double a0 = ar[kk], a1 = ar[lda + kk], a2 = ar[2 * lda + kk], a3 = ar[3 * lda + kk];
+                        const double2 b01 = *(const double2*)(br + kk * ldb);
+                        const double2 b23 = *(const double2*)(br + kk * ldb + 2);
+                        const double av[4] = {a0, a1, a2, a3}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+                        for (int r = 0; r < 4; r++)
+#pragma unroll
+                            for (int c = 0; c < 4; c++) acc[s][4 * r + c] += av[r] * bv[c];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int s = 0; s < kPanT; s++) {
+            const int tile = threadIdx.x + s * blockDim.x;
+            if (tile < ntile) {
+                const int ib = i0 + 4 * (tile / n4), jb = 4 * (tile % n4);
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+#pragma unroll
+                    for (int c = 0; c < 4; c++)
+                        if (ib + r < N && jb + c < N) C[(long)(ib + r) * N + jb + c] = alpha * acc[s][4 * r + c];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// C = op(A) op(B) (N x N): operands fully staged in LDS when full, else panels.
+__device__ __forceinline__ void wg_matmul(int N, const double* __restrict__ A, bool ta, const double* __restrict__ B,
+                                          bool tb, double* C, double* sm, int full)
+{
+    if (full) wg_matmul_full(N, A, ta, B, tb, C, sm);
+    else wg_matmul_panel(N, N, A, ta, B, tb, C, sm, 1.0);
+}
+
+extern __shared__ __align__(16) double smem_scf[];   // wg_matmul staging (full or panel)
 
 struct ScfArgs {
     const MolDesc* mol;
@@ -115,7 +194,6 @@ struct ScfArgs {
     double *Fp, *C, *eps;
     double *work;           // 3 * nmat
     double *Fh, *Eh;        // diis_space * nmat
-    int lds_mm;             // wg_matmul stages its operands in LDS (0: molecules too large)
     const double* exc;
     long nmat;
     double a0;
@@ -204,6 +282,7 @@ __device__ int diis_solve_dev(int n, const double* B, double* c)
 
 // error vector e = X^T (F P S - S P F) X, convergence test, DIIS push and
 // extrapolation, and F' = X^T Fbar X.
+template <bool FULL>
 __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
 {
     __shared__ double red[2 * kScfThreads / 64];
@@ -219,15 +298,15 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
     const double *F = g.F + o, *P = g.P + o, *S = g.S + o, *X = g.X + o;
     double *W0 = g.work + o, *W1 = g.work + g.nmat + o, *W2 = g.work + 2 * g.nmat + o;
     const int it = st.iter + 1;
-    wg_matmul(N, F, false, P, false, W0, g.lds_mm ? smem_scf : nullptr);
-    wg_matmul(N, W0, false, S, false, W1, g.lds_mm ? smem_scf : nullptr);     // FPS
+    wg_matmul(N, F, false, P, false, W0, smem_scf, FULL);
+    wg_matmul(N, W0, false, S, false, W1, smem_scf, FULL);     // FPS
     for (int t = threadIdx.x; t < NN; t += blockDim.x) {
         const int i = t / N, j = t % N;
         W0[t] = W1[i * N + j] - W1[j * N + i];
     }
     __syncthreads();
-    wg_matmul(N, X, true, W0, false, W2, g.lds_mm ? smem_scf : nullptr);
-    wg_matmul(N, W2, false, X, false, W0, g.lds_mm ? smem_scf : nullptr);     // e
+    wg_matmul(N, X, true, W0, false, W2, smem_scf, FULL);
+    wg_matmul(N, W2, false, X, false, W0, smem_scf, FULL);     // e
     double mx = 0.0;
     for (int t = threadIdx.x; t < NN; t += blockDim.x) mx = fmax(mx, fabs(W0[t]));
     const double err = block_max(mx, red);
@@ -288,8 +367,8 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
         __syncthreads();
         Fsrc = W1;
     }
-    wg_matmul(N, X, true, Fsrc, false, W2, g.lds_mm ? smem_scf : nullptr);
-    wg_matmul(N, W2, false, X, false, g.Fp + o, g.lds_mm ? smem_scf : nullptr);
+    wg_matmul(N, X, true, Fsrc, false, W2, smem_scf, FULL);
+    wg_matmul(N, W2, false, X, false, g.Fp + o, smem_scf, FULL);
     if (threadIdx.x == 0) {
         st.iter = it;
         st.err = err;
@@ -325,13 +404,14 @@ __global__ __launch_bounds__(kScfThreads) void atom_guess_kernel(const MolDesc* 
 }
 
 // W = X^T A X (guess from the core Hamiltonian)
+template <bool FULL>
 __global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const double* __restrict__ A)
 {
     const int m = blockIdx.x;
     const MolDesc md = g.mol[m];
     const long o = md.mat0;
-    wg_matmul(md.nbf, g.X + o, true, A + o, false, g.work + o, g.lds_mm ? smem_scf : nullptr);
-    wg_matmul(md.nbf, g.work + o, false, g.X + o, false, g.Fp + o, g.lds_mm ? smem_scf : nullptr);
+    wg_matmul(md.nbf, g.X + o, true, A + o, false, g.work + o, smem_scf, FULL);
+    wg_matmul(md.nbf, g.work + o, false, g.X + o, false, g.Fp + o, smem_scf, FULL);
 }
 
 // Symmetric eigenproblem, parallel-order cyclic Jacobi (round-robin pairing:
@@ -343,6 +423,7 @@ __global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const doub
 // (warm), the rotations start from V = W on A = W^T F' W, which is nearly
 // diagonal close to self-consistency, so few sweeps remain; the sorted
 // vectors are kept in `keep` for the next iteration.  tmp: N^2 scratch.
+template <bool GLOBAL>
 __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __restrict__ mols,
                                                            const MolState* __restrict__ state, int only_active,
                                                            const double* __restrict__ src, double* __restrict__ vecs,
@@ -356,10 +437,10 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
     const MolDesc md = mols[m];
     const int N = md.nbf, NN = N * N;
     extern __shared__ __align__(16) unsigned char smem_eig[];
-    // matrix and vectors in LDS, or (gws: molecules too large for LDS) in
-    // global memory after the warm-start scratch region
-    double* A = gws ? gws + nmat + md.mat0 : (double*)smem_eig;
-    double* Vv = gws ? gws + 2 * nmat + md.mat0 : A + NN;
+    // matrix and vectors in LDS, or (GLOBAL: molecules too large for LDS) in
+    // global memory after the warm-start scratch region of gws
+    double* A = GLOBAL ? gws + nmat + md.mat0 : (double*)smem_eig;
+    double* Vv = GLOBAL ? gws + 2 * nmat + md.mat0 : A + NN;
     __shared__ int rp[kMaxNbf / 2 + 1], rq[kMaxNbf / 2 + 1];
     __shared__ double rc[kMaxNbf / 2 + 1], rs[kMaxNbf / 2 + 1];
     __shared__ double red[2 * kScfThreads / 64];
@@ -371,7 +452,20 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
         Vv[t] = use_warm ? warm[md.mat0 + t] : ((t / N == t % N) ? 1.0 : 0.0);
     }
     __syncthreads();
-    if (use_warm) {
+    if (use_warm && GLOBAL) {
+        double* T = tmp + md.mat0;
+        wg_matmul_panel(N, N, A, false, Vv, false, T, (double*)smem_eig, 1.0);   // T = F' W
+        wg_matmul_panel(N, N, Vv, true, T, false, A, (double*)smem_eig, 1.0);    // A = W^T T
+        for (int t = threadIdx.x; t < NN; t += blockDim.x) {      // symmetrise
+            const int i = t / N, j = t % N;
+            if (i < j) {
+                const double s = 0.5 * (A[i * N + j] + A[j * N + i]);
+                A[i * N + j] = s;
+                A[j * N + i] = s;
+            }
+        }
+        __syncthreads();
+    } else if (use_warm) {
         double* T = tmp + md.mat0;
         for (int t = threadIdx.x; t < NN; t += blockDim.x) {      // T = F' W
             const int i = t / N, j = t % N;
@@ -438,8 +532,9 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
                 A[q * N + j] = s * apj + c * aqj;
             }
             __syncthreads();
+            // columns: lanes take the planes of one row (contiguous columns)
             for (int idx = threadIdx.x; idx < half * N; idx += blockDim.x) {
-                const int k = idx / N, i = idx % N;
+                const int i = idx / half, k = idx % half;
                 if (rq[k] >= N || rs[k] == 0.0) continue;
                 const int p = rp[k], q = rq[k];
                 const double c = rc[k], s = rs[k];
@@ -474,26 +569,25 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
 }
 
 // X = U s^-1/2 U^T from eigh(S) (vectors in C, values in eps); flags near-singular S.
-__global__ __launch_bounds__(kScfThreads) void lowdin_kernel(const MolDesc* __restrict__ mols, MolState* state,
-                                                             const double* __restrict__ U, const double* __restrict__ s,
-                                                             double* __restrict__ X)
+// The scaled vectors W = U s^-1/2 go to work, then X = W U^T.
+template <bool FULL>
+__global__ __launch_bounds__(kScfThreads) void lowdin_kernel(ScfArgs g)
 {
     const int m = blockIdx.x;
-    const MolDesc md = mols[m];
+    const MolDesc md = g.mol[m];
     const int N = md.nbf;
-    const double* u = U + md.mat0;
-    const double* w = s + md.ao0;
-    if (threadIdx.x == 0 && w[0] < 1e-8) state[m].status = -1;
-    for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
-        const int i = t / N, j = t % N;
-        double acc = 0.0;
-        for (int k = 0; k < N; k++) acc += u[i * N + k] * u[j * N + k] / sqrt(fmax(w[k], 1e-300));
-        X[md.mat0 + t] = acc;
-    }
+    const long o = md.mat0;
+    const double* u = g.C + o;
+    const double* w = g.eps + md.ao0;
+    if (threadIdx.x == 0 && w[0] < 1e-8) g.state[m].status = -1;
+    for (int t = threadIdx.x; t < N * N; t += blockDim.x) g.work[o + t] = u[t] / sqrt(fmax(w[t % N], 1e-300));
+    __syncthreads();
+    wg_matmul(N, g.work + o, false, u, true, (double*)g.X + o, smem_scf, FULL);
 }
 
 // C = X C'; unless this was the final iteration, P = 2 C_occ C_occ^T.
 // Final iterations keep P (the density that produced the last F) and retire.
+template <bool FULL>
 __global__ __launch_bounds__(kScfThreads) void density_kernel(ScfArgs g, int guess)
 {
     const int m = blockIdx.x;
@@ -503,18 +597,16 @@ __global__ __launch_bounds__(kScfThreads) void density_kernel(ScfArgs g, int gue
     const int N = md.nbf, no = md.nocc;
     const long o = md.mat0;
     const int fin = guess ? 0 : st.final_;
-    wg_matmul(N, g.X + o, false, g.Fp + o, false, g.C + o, g.lds_mm ? smem_scf : nullptr);   // Fp holds C' here
-    if (!fin) {
-        const double* Cs = g.C + o;
-        if (g.lds_mm) {
-            for (int t = threadIdx.x; t < N * N; t += blockDim.x) smem_scf[t] = g.C[o + t];
-            __syncthreads();
-            Cs = smem_scf;
-        }
+    wg_matmul(N, g.X + o, false, g.Fp + o, false, g.C + o, smem_scf, FULL);   // Fp holds C' here
+    if (!fin && !FULL) {
+        wg_matmul_panel(N, no, g.C + o, false, g.C + o, true, g.P + o, smem_scf, 2.0);
+    } else if (!fin) {
+        for (int t = threadIdx.x; t < N * N; t += blockDim.x) smem_scf[t] = g.C[o + t];
+        __syncthreads();
         for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
             const int i = t / N, j = t % N;
             double s = 0.0;
-            for (int k = 0; k < no; k++) s += Cs[i * N + k] * Cs[j * N + k];
+            for (int k = 0; k < no; k++) s += smem_scf[i * N + k] * smem_scf[j * N + k];
             g.P[o + t] = 2.0 * s;
         }
     }
@@ -573,7 +665,6 @@ static ScfArgs scf_args(ks_batch* b, bool only_active)
     g.max_iter = b->opt.max_iter;
     g.diis_space = b->opt.diis_space;
     g.only_active = only_active;
-    g.lds_mm = matmul_fits(b);
     return g;
 }
 
@@ -581,7 +672,7 @@ static ScfArgs scf_args(ks_batch* b, bool only_active)
 static size_t matmul_lds(const ks_batch* b)
 {
     const size_t n = max_nbf(b);
-    return matmul_fits(b) ? sizeof(double) * (2 * n * n + 4) : 0;
+    return matmul_fits(b) ? sizeof(double) * (2 * n * n + 4) : sizeof(double) * panel_lds_doubles((int)n);
 }
 
 static bool eigh_fits(const ks_batch* b)
@@ -590,10 +681,27 @@ static bool eigh_fits(const ks_batch* b)
     return 2 * sizeof(double) * n * n <= kScfLds;
 }
 
+// matrix and vectors in LDS, or (global mode) the panel staging of the
+// warm-start products
 static size_t eigh_lds(const ks_batch* b)
 {
     const size_t n = max_nbf(b);
-    return eigh_fits(b) ? 2 * sizeof(double) * n * n : 0;
+    return eigh_fits(b) ? 2 * sizeof(double) * n * n : sizeof(double) * panel_lds_doubles((int)n);
+}
+
+// One work group per molecule: kern<true> when wg_matmul's operands fit in
+// LDS whole, else kern<false> (panel staging).
+template <typename K1, typename K0, typename... Args>
+static ks_status launch_mm(ks_batch* b, K1 kfull, K0 kpanel, Args... args)
+{
+    const bool full = matmul_fits(b);
+    const size_t lds = matmul_lds(b);
+    KS_HIP(hipFuncSetAttribute(full ? (const void*)kfull : (const void*)kpanel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (full) hipLaunchKernelGGL(kfull, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, args...);
+    else hipLaunchKernelGGL(kpanel, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, args...);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
 }
 
 // warm == nullptr: cold start from the identity.  Otherwise warm/keep hold the
@@ -602,10 +710,16 @@ static ks_status run_eigh(ks_batch* b, bool only_active, const double* src, doub
                           double* warm = nullptr)
 {
     const size_t lds = eigh_lds(b);
-    KS_HIP(hipFuncSetAttribute((const void*)eigh_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(eigh_kernel, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, b->d_mol, b->d_state,
-                       (int)only_active, src, vecs, vals, (const double*)warm, warm, warm ? b->d_work : nullptr,
-                       warm ? b->d_have_warm : nullptr, eigh_fits(b) ? nullptr : b->d_work, b->nmat);
+    const void* fn = eigh_fits(b) ? (const void*)eigh_kernel<false> : (const void*)eigh_kernel<true>;
+    KS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (eigh_fits(b))
+        hipLaunchKernelGGL(eigh_kernel<false>, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, b->d_mol,
+                           b->d_state, (int)only_active, src, vecs, vals, (const double*)warm, warm,
+                           warm ? b->d_work : nullptr, warm ? b->d_have_warm : nullptr, nullptr, b->nmat);
+    else
+        hipLaunchKernelGGL(eigh_kernel<true>, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, b->d_mol,
+                           b->d_state, (int)only_active, src, vecs, vals, (const double*)warm, warm,
+                           warm ? b->d_work : nullptr, warm ? b->d_have_warm : nullptr, b->d_work, b->nmat);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
@@ -628,10 +742,7 @@ ks_status launch_lowdin(ks_batch* b)
     KTimer tm(b, "lowdin");
     ks_status st = run_eigh(b, false, b->d_S, b->d_C, b->d_eps);
     if (st) return st;
-    hipLaunchKernelGGL(lowdin_kernel, dim3(b->n_mol), dim3(kScfThreads), 0, b->stream, b->d_mol, b->d_state, b->d_C,
-                       b->d_eps, b->d_X);
-    KS_HIP(hipGetLastError());
-    return KS_OK;
+    return launch_mm(b, lowdin_kernel<true>, lowdin_kernel<false>, scf_args(b, false));
 }
 
 ks_status launch_guess(ks_batch* b)
@@ -644,15 +755,11 @@ ks_status launch_guess(ks_batch* b)
         return KS_OK;
     }
     ScfArgs g = scf_args(b, false);
-    KS_HIP(hipFuncSetAttribute((const void*)xtax_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
-    hipLaunchKernelGGL(xtax_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g, (const double*)b->d_H);
-    KS_HIP(hipGetLastError());
-    ks_status st = run_eigh(b, false, b->d_Fp, b->d_Fp, b->d_eps);
+    ks_status st = launch_mm(b, xtax_kernel<true>, xtax_kernel<false>, g, (const double*)b->d_H);
     if (st) return st;
-    KS_HIP(hipFuncSetAttribute((const void*)density_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
-    hipLaunchKernelGGL(density_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g, 1);
-    KS_HIP(hipGetLastError());
-    return KS_OK;
+    st = run_eigh(b, false, b->d_Fp, b->d_Fp, b->d_eps);
+    if (st) return st;
+    return launch_mm(b, density_kernel<true>, density_kernel<false>, g, 1);
 }
 
 ks_status launch_iteration_tail(ks_batch* b)
@@ -660,9 +767,8 @@ ks_status launch_iteration_tail(ks_batch* b)
     ScfArgs g = scf_args(b, true);
     {
         KTimer tm(b, "diis");
-        KS_HIP(hipFuncSetAttribute((const void*)diis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
-        hipLaunchKernelGGL(diis_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g);
-        KS_HIP(hipGetLastError());
+        ks_status st = launch_mm(b, diis_kernel<true>, diis_kernel<false>, g);
+        if (st) return st;
     }
     {
         KTimer tm(b, "eigh");
@@ -671,9 +777,8 @@ ks_status launch_iteration_tail(ks_batch* b)
     }
     {
         KTimer tm(b, "density");
-        KS_HIP(hipFuncSetAttribute((const void*)density_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)matmul_lds(b)));
-        hipLaunchKernelGGL(density_kernel, dim3(b->n_mol), dim3(kScfThreads), matmul_lds(b), b->stream, g, 0);
-        KS_HIP(hipGetLastError());
+        ks_status st = launch_mm(b, density_kernel<true>, density_kernel<false>, g, 0);
+        if (st) return st;
     }
     return KS_OK;
 }

@@ -26,10 +26,11 @@ namespace ks {
 // ---------------------------------------------------------------------------
 // Becke's smoothing polynomial applied three times, f3(mu); the cell
 // function is s(mu) = (1 - f3(mu))/2, and f3 is odd, so s(-mu) = (1 + f3(mu))/2.
-__device__ __forceinline__ double becke_f3(double mu)
+template <typename T>
+__device__ __forceinline__ T becke_f3(T mu)
 {
 #pragma unroll
-    for (int k = 0; k < 3; k++) mu = 1.5 * mu - 0.5 * mu * mu * mu;
+    for (int k = 0; k < 3; k++) mu = T(1.5) * mu - T(0.5) * mu * mu * mu;
     return mu;
 }
 
@@ -38,7 +39,10 @@ __device__ __forceinline__ double becke_f3(double mu)
 // every atom and the cell products P_a (both transposed: [atom][thread]).
 // Each atom pair (a < c) evaluates f3 once: s(mu_ac) multiplies P_a and
 // s(mu_ca) = s(-mu_ac) multiplies P_c, so every P_a receives its factors in
-// ascending order of the other atom.
+// ascending order of the other atom.  Points are placed in FP64; the cell
+// functions run in T (FP32 in the mixed path: half the LDS per thread, so
+// twice the resident waves, at twice the vector rate).
+template <typename T>
 __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mols, const double* __restrict__ Rat,
                                                   const double* __restrict__ radial, const double* __restrict__ ang,
                                                   int nrad, int nth, int nph, double* __restrict__ out)
@@ -50,16 +54,16 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
     const int na = md.natom;
     const int bs = blockDim.x, t = threadIdx.x;
     double* Ra = smem_grid;                       // [natom][3]
-    double* invR = Ra + 3 * na;                   // [natom][natom]: 1/|R_a - R_c|
-    double* dist = invR + na * na;                // [natom][bs]
-    double* Pc = dist + na * bs;                  // [natom][bs]
+    T* invR = (T*)(Ra + 3 * na);                  // [natom][natom]: 1/|R_a - R_c|
+    T* dist = invR + na * na;                     // [natom][bs]
+    T* Pc = dist + na * bs;                       // [natom][bs]
     for (int i = threadIdx.x; i < 3 * na; i += blockDim.x) Ra[i] = Rat[3 * md.atom0 + i];
     for (int i = threadIdx.x; i < na * na; i += blockDim.x) {
         const int a = i / na, c = i % na;
         const double* pa = Rat + 3 * (md.atom0 + a);
         const double* pc = Rat + 3 * (md.atom0 + c);
         const double dx = pa[0] - pc[0], dy = pa[1] - pc[1], dz = pa[2] - pc[2];
-        invR[i] = a == c ? 0.0 : 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        invR[i] = a == c ? T(0) : T(1.0 / sqrt(dx * dx + dy * dy + dz * dz));
     }
     __syncthreads();
     if (l >= md.ngrid) return;
@@ -77,23 +81,23 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
     p[2] = Ra[3 * A + 2] + r * ct;
     for (int a = 0; a < na; a++) {
         const double dx = p[0] - Ra[3 * a], dy = p[1] - Ra[3 * a + 1], dz = p[2] - Ra[3 * a + 2];
-        dist[a * bs + t] = sqrt(dx * dx + dy * dy + dz * dz);
-        Pc[a * bs + t] = 1.0;
+        dist[a * bs + t] = T(sqrt(dx * dx + dy * dy + dz * dz));
+        Pc[a * bs + t] = T(1);
     }
-    double num = 0.0, den = 0.0;
+    T num = T(0), den = T(0);
     for (int a = 0; a < na; a++) {
-        const double ra = dist[a * bs + t];
-        const double* ir = invR + a * na;
-        double Pa = Pc[a * bs + t];
+        const T ra = dist[a * bs + t];
+        const T* ir = invR + a * na;
+        T Pa = Pc[a * bs + t];
         for (int c = a + 1; c < na; c++) {
-            const double f = becke_f3((ra - dist[c * bs + t]) * ir[c]);
-            Pa *= 0.5 * (1.0 - f);
-            Pc[c * bs + t] *= 0.5 * (1.0 + f);
+            const T f = becke_f3<T>((ra - dist[c * bs + t]) * ir[c]);
+            Pa *= T(0.5) * (T(1) - f);
+            Pc[c * bs + t] *= T(0.5) * (T(1) + f);
         }
         if (a == A) num = Pa;
         den += Pa;
     }
-    const double w = radial[nrad + i] * ang[nth + j] * (2.0 * kPi / nph) * (num / den);
+    const double w = radial[nrad + i] * ang[nth + j] * (2.0 * kPi / nph) * ((double)num / (double)den);
     double* o = out + 4 * (md.grid0 + l);
     o[0] = p[0];
     o[1] = p[1];
@@ -101,9 +105,9 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
     o[3] = w;
 }
 
-ks_status launch_grid(ks_batch* b, hipStream_t s)
+template <typename T>
+static ks_status run_grid(ks_batch* b, hipStream_t s)
 {
-    KTimer tm(b, "grid", s);
     long maxg = 0;
     int maxat = 0;
     for (auto& m : b->mol) {
@@ -111,18 +115,26 @@ ks_status launch_grid(ks_batch* b, hipStream_t s)
         maxat = std::max(maxat, m.natom);
     }
     int bs = 64;
-    auto lds_for = [&](int n) { return sizeof(double) * (3 * maxat + (size_t)maxat * maxat + 2 * (size_t)maxat * n); };
+    auto lds_for = [&](int n) {
+        return sizeof(double) * 3 * maxat + sizeof(T) * ((size_t)maxat * maxat + 2 * (size_t)maxat * n);
+    };
     while (bs > 16 && lds_for(bs) > 163840) bs /= 2;
     const size_t lds = lds_for(bs);
     if (lds > 163840) {
         set_error("grid: %d atoms exceed the LDS budget", maxat);
         return KS_EUNSUPPORTED;
     }
-    KS_HIP(hipFuncSetAttribute((const void*)grid_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(grid_kernel, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, s,
+    KS_HIP(hipFuncSetAttribute((const void*)grid_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(grid_kernel<T>, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, s,
                        b->d_mol, b->d_R, b->d_radial, b->d_ang, b->opt.n_rad, b->opt.n_theta, b->opt.n_phi, b->d_grid);
     KS_HIP(hipGetLastError());
     return KS_OK;
+}
+
+ks_status launch_grid(ks_batch* b, hipStream_t s)
+{
+    KTimer tm(b, "grid", s);
+    return b->opt.prec == KS_MIXED ? run_grid<float>(b, s) : run_grid<double>(b, s);
 }
 
 // ---------------------------------------------------------------------------

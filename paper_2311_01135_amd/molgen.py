@@ -208,7 +208,62 @@ def tree(n_heavy: int, seed: int, index: int, max_tries: int = 1000):
         Zarr = np.array(Z, dtype=np.int32)
         assert int(Zarr.sum()) == 8 * n_heavy + 2
         return Zarr, xyz
+    # Large trees rarely come out clash-free as a whole; continue the same
+    # stream with placements checked atom by atom (a clashing direction is
+    # drawn again; a molecule that cannot be completed is started over).
+    for _ in range(max_tries):
+        got = _tree_checked(rng, n_heavy)
+        if got is not None:
+            return got
     raise RuntimeError("tree(): no acceptable molecule after %d draws" % max_tries)
+
+
+def _place(rng, pos, dirs, p, length, max_local=100):
+    """Direction and position of a new bond from atom p keeping every other
+    atom at least 0.9 A away, or None."""
+    for _ in range(max_local):
+        d = _new_direction(rng, dirs[p])
+        x = pos[p] + length * d
+        if all(np.linalg.norm(x - q) >= 0.9 for q in pos):
+            return d, x
+    return None
+
+
+def _tree_checked(rng, n_heavy):
+    Z = [_draw_element(rng)]
+    pos = [np.zeros(3)]
+    dirs = [[]]
+    free = [VALENCE[Z[0]]]
+    for _k in range(1, n_heavy):
+        cand = [i for i in range(len(Z)) if free[i] > 0]
+        if not cand:
+            return None
+        z = _draw_element(rng)
+        p = cand[rng.randint(len(cand))]
+        got = _place(rng, pos, dirs, p, rng.uniform(1.40, 1.52))
+        if got is None:
+            return None
+        d, x = got
+        Z.append(z)
+        pos.append(x)
+        dirs[p].append(d)
+        dirs.append([-d])
+        free[p] -= 1
+        free.append(VALENCE[z] - 1)
+    for i in range(n_heavy):
+        while free[i] > 0:
+            got = _place(rng, pos, dirs, i, 1.09)
+            if got is None:
+                return None
+            d, x = got
+            Z.append(1)
+            pos.append(x)
+            dirs[i].append(d)
+            free[i] -= 1
+    xyz = np.array(pos)
+    Zarr = np.array(Z, dtype=np.int32)
+    assert int(Zarr.sum()) == 8 * n_heavy + 2 and _min_dist(xyz) >= 0.9
+    return Zarr, xyz
 
 
 def batch(n_mol: int, seed: int, n_heavy=9, start: int = 0):

@@ -1,7 +1,8 @@
-"""Full-size parity: the benchmark's own batch (256 molecules, 9-11 heavy
-atoms, seed 2) in the launch configuration bench.py times, compared on
-sampled molecules with oracle SCF results written by
-tests/golden/make_golden.py, plus properties that hold for every molecule;
+"""Full-size parity: the benchmark's own batch (4096 molecules, 9-11 heavy
+atoms, seed 2) in the launch configuration bench.py times, compared with
+oracle SCF results for its first 64 molecules (written by
+tests/golden/make_golden_subset.py) and two later samples (written by
+tests/golden/make_golden.py), plus properties that hold for every molecule;
 and full-grid kernel parity for one 9-heavy-atom molecule.
 
 Tolerances: FP64 |dE|, |d gap| <= 1e-8 Ha and iterations within 1; mixed
@@ -14,12 +15,15 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from paper_2311_01135_amd import molgen
+from paper_2311_01135_amd import autotune, molgen
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_scf_samples.json")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+GOLD = os.path.join(GOLDEN, "oracle_scf_samples.json")
+SUBSET = os.path.join(GOLDEN, "oracle_scf_seed2_first64.json")
+N_BENCH = 4096
 
 
 @pytest.fixture(scope="module")
@@ -38,18 +42,28 @@ def gold():
 
 
 @pytest.fixture(scope="module")
+def bench_refs(gold):
+    with open(SUBSET) as f:
+        sub = json.load(f)["molecules"]
+    seen = {g["index"] for g in sub}
+    extra = [g for g in gold["molecules"] if g["set"] == "bench_9-11_seed2" and g["index"] not in seen]
+    return sub + extra
+
+
+@pytest.fixture(scope="module")
 def bench_mols():
-    return molgen.batch(256, 2, (9, 11))
+    return molgen.batch(N_BENCH, 2, (9, 11))
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-def test_bench_batch_vs_oracle_samples(ks, gold, bench_mols, prec):
+def test_bench_batch_vs_oracle_samples(ks, bench_refs, bench_mols, prec):
     tol = 1e-4 if prec == 1 else 1e-8
-    with ks.Batch(bench_mols, prec=prec) as b:
+    opts = autotune.tuned_options(prec, [molgen.nbf_sto3g(z) for z, _ in bench_mols])
+    print("batch %d molecules, prec %d, options %s" % (len(bench_mols), prec, opts), flush=True)
+    assert len(bench_refs) >= 64
+    with ks.Batch(bench_mols, prec=prec, **opts) as b:
         b.scf_solve()
-        for g in gold["molecules"]:
-            if g["set"] != "bench_9-11_seed2":
-                continue
+        for g in bench_refs:
             r = b.result(g["index"])
             assert r["status"] == 1
             assert abs(r["E"] - g["E"]) <= tol, (g["index"], r["E"], g["E"])

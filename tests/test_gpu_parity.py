@@ -89,6 +89,23 @@ def test_grid(small):
         assert np.abs(got[:, 3] - ref[:, 3]).max() <= 1e-12 * np.abs(ref[:, 3]).max()
 
 
+def test_grid_mixed(ks):
+    # The mixed path evaluates the Becke cell functions in FP32: mu carries
+    # ~1e-7 relative error, |d s / d mu| <= (3/2)^3 / 2 ~ 1.7, and a cell
+    # product has at most ~30 factors, so each weight is within ~1e-5 of its
+    # FP64 value relative to the largest weight; the points stay FP64.
+    mols = _mols_small()
+    with ks.Batch(mols, prec=ks.KS_MIXED) as b:
+        b.setup()
+        for m, (z, x) in enumerate(mols):
+            ref = O.Mol(z, x).grid()
+            got = b.grid(m)
+            assert np.abs(got[:, :3] - ref[:, :3]).max() < 1e-12
+            assert np.abs(got[:, 3] - ref[:, 3]).max() <= 1e-5 * np.abs(ref[:, 3]).max(), m
+            # the integrated weight (the volume the grid covers) moves far less
+            assert abs(got[:, 3].sum() - ref[:, 3].sum()) <= 1e-6 * abs(ref[:, 3]).sum(), m
+
+
 def _rand_density(o, seed):
     # a symmetric density-like matrix: 2 C C^T of random orthonormal-ish orbitals
     rng = np.random.default_rng(seed)
