@@ -108,3 +108,81 @@ __device__ __forceinline__ void jk_scatter(const A (&I)[NA * NB * NC * ND], int 
 }
 
 }  // namespace ks
+
+namespace ks {
+
+// Bra-major scatter for work groups whose J/K partials live in global
+// memory: every lane holds a quartet of the same bra pair (ab).  Pa, Pb: LDS
+// copies of the density rows of the bra's shells ([NA][N], [NB][N]); Pg: the
+// density in global memory (for P_cd); pab: P_ab of the bra.  J_ab
+// accumulates in the caller's registers (jab, with the factor 2 f), J_cd
+// goes to the global partial AJ, and K_ac, K_ad (K_bc, K_bd) to the LDS rows
+// Ka (Kb) of the bra's shells, which the caller adds to the partial K once
+// per bra.  Same per-component terms as jk_scatter.
+template <int NA, int NB, int NC, int ND, typename A>
+__device__ __forceinline__ void jk_scatter_rows(const A (&I)[NA * NB * NC * ND], int oc, int od, A f, int N,
+                                                const A* Pa, const A* Pb, const A* __restrict__ Pg,
+                                                const A (&pab)[NA][NB], A (&jab)[NA][NB], A* AJ, A* Ka, A* Kb)
+{
+    A pcd[NC][ND], pbd[NB][ND], pbc[NB][NC], pad[NA][ND], pac[NA][NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+        for (int d = 0; d < ND; d++) pcd[c][d] = Pg[(oc + c) * N + od + d];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+#pragma unroll
+        for (int d = 0; d < ND; d++) pbd[b][d] = Pb[b * N + od + d];
+#pragma unroll
+        for (int c = 0; c < NC; c++) pbc[b][c] = Pb[b * N + oc + c];
+    }
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+#pragma unroll
+        for (int d = 0; d < ND; d++) pad[a][d] = Pa[a * N + od + d];
+#pragma unroll
+        for (int c = 0; c < NC; c++) pac[a][c] = Pa[a * N + oc + c];
+    }
+    A jb[NA][NB] = {}, jcd[NC][ND] = {}, kac[NA][NC] = {}, kbc[NB][NC] = {}, kad[NA][ND] = {}, kbd[NB][ND] = {};
+#pragma unroll
+    for (int a = 0; a < NA; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int d = 0; d < ND; d++) {
+                    const A v = I[((a * NB + b) * NC + c) * ND + d];
+                    jb[a][b] += v * pcd[c][d];
+                    jcd[c][d] += v * pab[a][b];
+                    kac[a][c] += v * pbd[b][d];
+                    kbc[b][c] += v * pad[a][d];
+                    kad[a][d] += v * pbc[b][c];
+                    kbd[b][d] += v * pac[a][c];
+                }
+    const A f2 = A(2) * f;
+#pragma unroll
+    for (int a = 0; a < NA; a++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) jab[a][b] += f2 * jb[a][b];
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+        for (int d = 0; d < ND; d++) lds_add(&AJ[(oc + c) * N + od + d], f2 * jcd[c][d]);
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+#pragma unroll
+        for (int c = 0; c < NC; c++) lds_add(&Ka[a * N + oc + c], f * kac[a][c]);
+#pragma unroll
+        for (int d = 0; d < ND; d++) lds_add(&Ka[a * N + od + d], f * kad[a][d]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+#pragma unroll
+        for (int c = 0; c < NC; c++) lds_add(&Kb[b * N + oc + c], f * kbc[b][c]);
+#pragma unroll
+        for (int d = 0; d < ND; d++) lds_add(&Kb[b * N + od + d], f * kbd[b][d]);
+    }
+}
+
+}  // namespace ks

@@ -496,7 +496,8 @@ struct DirectArgs {
     const double* pp[3];
     long npp[3];
     const double* Q[3];
-    const double* tab;
+    const double* tab;      // Boys table, FP64
+    const float* tabf;      // Boys table, FP32 (integrals evaluated in FP32: the mixed path)
     const double* P;
     const double* Pref;     // incremental build: digest P - Pref
     const double* dP;       // global mode: the digested density (materialised)
@@ -509,7 +510,23 @@ struct DirectArgs {
 
 constexpr int kDirectThreads = 256;
 
-template <int LA, int LB, int LC, int LD, typename A>
+template <typename R> __device__ __forceinline__ const R* direct_tab(const DirectArgs& g);
+template <> __device__ __forceinline__ const double* direct_tab<double>(const DirectArgs& g) { return g.tab; }
+template <> __device__ __forceinline__ const float* direct_tab<float>(const DirectArgs& g) { return g.tabf; }
+
+// work-group maximum (every thread gets it); ends with a barrier
+__device__ __forceinline__ double block_max_direct(double mx, double* red)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) r = fmax(r, red[w]);
+    return r;
+}
+
+template <int LA, int LB, int LC, int LD, typename A, typename R>
 __device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc& md, int chunk, int nchunk, double pmax,
                                              const A* __restrict__ Ps, A* AJ, A* AK)
 {
@@ -532,8 +549,8 @@ __device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc&
         const Pair P1 = g.pairs[cb][ib], P2 = g.pairs[ck][ik];
         const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
         const PairView vb{g.pp[cb], g.npp[cb], ib}, vk{g.pp[ck], g.npp[ck], ik};
-        double I[NCOMP];
-        eri_quartet<LA, LB, LC, LD, double>(sa, sb, sc, sd, vb, vk, g.tab, g.cut, I);
+        R I[NCOMP];
+        eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, direct_tab<R>(g), R(g.cut), I);
         A Ia[NCOMP];
 #pragma unroll
         for (int k = 0; k < NCOMP; k++) Ia[k] = A(I[k]);
@@ -546,9 +563,98 @@ __device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc&
     }
 }
 
-// GLOBAL: molecules whose accumulators exceed the LDS; the density comes
-// from dP and the scatter goes to this item's global partial matrices.
-template <typename A, bool GLOBAL>
+// Large molecules (partials in global memory): the work group walks its
+// quartet range one bra pair at a time.  Per bra the density rows of its two
+// shells are staged in LDS (Prow) and their K rows accumulate in LDS (Krow,
+// K_ac, K_ad, K_bc, K_bd), J_ab in registers; both are added to the partials
+// once per bra, so only J_cd reaches global memory per quartet.
+template <int LA, int LB, int LC, int LD, typename R>
+__device__ __forceinline__ void direct_class_rows(const DirectArgs& g, const MolDesc& md, int chunk, int nchunk,
+                                                  double pmax, const double* __restrict__ Pg, double* AJ, double* AK,
+                                                  double* Prow, double* Krow)
+{
+    constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
+    constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
+    constexpr int NCOMP = NA * NB * NC * ND;
+    const int N = md.nbf;
+    const long nq = md.nq[C];
+    const long lo = nq * chunk / nchunk, hi = nq * (chunk + 1) / nchunk;
+    if (lo >= hi) return;
+    const int cb = class_bra(C), ck = class_ket(C);
+    const int nket = md.npair[ck];
+    const double* __restrict__ Qb = g.Q[cb] + md.pair0[cb];
+    const double* __restrict__ Qk = g.Q[ck] + md.pair0[ck];
+    const double qtol = pmax > 0.0 ? g.tol / pmax : 1e300;
+    int i, j0;
+    decode_quartet(C, lo, nket, i, j0);
+    for (long q = lo; q < hi; i++, j0 = 0) {
+        const int nk = class_tri(C) ? i + 1 : nket;
+        const int seg = (int)min((long)(nk - j0), hi - q);
+        q += seg;
+        const int ib = md.pair0[cb] + i;
+        const int2 A1 = g.pao[cb][ib];
+        const int oa = A1.x & 0xffff, ob = A1.y;
+        const bool same = (A1.x >> 16) != 0;
+        for (int t = threadIdx.x; t < (NA + NB) * N; t += blockDim.x) {
+            const int r = t / N, col = t % N;
+            Prow[t] = Pg[(r < NA ? oa + r : ob + r - NA) * N + col];
+            Krow[t] = 0.0;
+        }
+        __syncthreads();
+        double pab[NA][NB], jab[NA][NB];
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                pab[a][b] = Prow[a * N + ob + b];
+                jab[a][b] = 0.0;
+            }
+        const double qb = Qb[i];
+        const Pair P1 = g.pairs[cb][ib];
+        const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb];
+        const PairView vb{g.pp[cb], g.npp[cb], ib};
+        for (int t = threadIdx.x; t < seg; t += blockDim.x) {
+            const int j = j0 + t;
+            if (qb * Qk[j] < qtol) continue;
+            const int ik = md.pair0[ck] + j;
+            const Pair P2 = g.pairs[ck][ik];
+            const Shell sc = g.shells[P2.sa], sd = g.shells[P2.sb];
+            const PairView vk{g.pp[ck], g.npp[ck], ik};
+            R Ir[NCOMP];
+            eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, direct_tab<R>(g), R(g.cut), Ir);
+            double I[NCOMP];
+#pragma unroll
+            for (int k = 0; k < NCOMP; k++) I[k] = double(Ir[k]);
+            const int2 A2 = g.pao[ck][ik];
+            double f = same ? 0.5 : 1.0;
+            if (A2.x >> 16) f *= 0.5;
+            if (class_tri(C) && i == j) f *= 0.5;
+            jk_scatter_rows<NA, NB, NC, ND, double>(I, A2.x & 0xffff, A2.y, f, N, Prow, Prow + NA * N, Pg, pab,
+                                                    jab, AJ, Krow, Krow + NA * N);
+        }
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                double v = jab[a][b];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                if ((threadIdx.x & 63) == 0 && v != 0.0) lds_add(&AJ[(oa + a) * N + ob + b], v);
+            }
+        __syncthreads();
+        // a same-shell pair's b rows are its a rows
+        for (int t = threadIdx.x; t < (same ? NA : NA + NB) * N; t += blockDim.x) {
+            const int r = t / N, col = t % N;
+            const double v = same ? Krow[t] + Krow[t + NA * N] : Krow[t];
+            if (v != 0.0) lds_add(&AK[(r < NA ? oa + r : ob + r - NA) * N + col], v);
+        }
+        __syncthreads();
+    }
+}
+
+// Molecules whose J/K accumulators fit in LDS: ΔP, J and K in LDS, all six
+// classes in one work group per item, the accumulators written out once.
+template <typename A, typename R>
 __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
 {
     const JkItem it = g.items[blockIdx.x];
@@ -556,17 +662,9 @@ __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
     const MolDesc md = g.mol[it.mol];
     const int N = md.nbf, NN = N * N;
     extern __shared__ __align__(16) unsigned char smem_direct[];
-    A *Pl, *AJ, *AK;
-    if constexpr (GLOBAL) {
-        Pl = (A*)(g.dP + md.mat0);
-        AJ = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
-        AK = AJ + g.part_stride;
-    } else {
-        Pl = (A*)smem_direct;
-        AJ = Pl + NN;
-        AK = AJ + NN;
-    }
-    const A* Ps = Pl;
+    A* Pl = (A*)smem_direct;
+    A* AJ = Pl + NN;
+    A* AK = AJ + NN;
     __shared__ double red[kDirectThreads / 64];
     const double* P = g.P + md.mat0;
     const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
@@ -574,30 +672,52 @@ __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
         const double v = Pr ? P[i] - Pr[i] : P[i];
         mx = fmax(mx, fabs(v));
-        if constexpr (!GLOBAL) Pl[i] = A(v);
+        Pl[i] = A(v);
         AJ[i] = A(0);
         AK[i] = A(0);
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    const double pmax = block_max_direct(mx, red);
+    direct_class<0, 0, 0, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 0, 0, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 0, 1, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 1, 0, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 1, 1, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 1, 1, 1, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
     __syncthreads();
-    double pmax = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); w++) pmax = fmax(pmax, red[w]);
-    direct_class<0, 0, 0, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
-    direct_class<1, 0, 0, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
-    direct_class<1, 0, 1, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
-    direct_class<1, 1, 0, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
-    direct_class<1, 1, 1, 0, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
-    direct_class<1, 1, 1, 1, A>(g, md, it.chunk, it.nchunk, pmax, Ps, AJ, AK);
-    if constexpr (!GLOBAL) {
-        __syncthreads();
-        A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-            out[i] = AJ[i];
-            out[g.part_stride + i] = AK[i];
+    A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        out[i] = AJ[i];
+        out[g.part_stride + i] = AK[i];
+    }
+}
+
+// Larger molecules: one launch per class (each class gets its own register
+// allocation), ΔP materialised in global memory (dP), J/K partials per item
+// in global memory, zeroed by the first launch.
+template <int LA, int LB, int LC, int LD, typename R>
+__global__ __launch_bounds__(kDirectThreads) void direct_rows_kernel(DirectArgs g, int zero)
+{
+    const JkItem it = g.items[blockIdx.x];
+    if (g.only_active && g.state[it.mol].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = g.mol[it.mol];
+    const int N = md.nbf, NN = N * N;
+    extern __shared__ __align__(16) unsigned char smem_direct[];
+    double* AJ = (double*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+    double* AK = AJ + g.part_stride;
+    const double* dP = g.dP + md.mat0;
+    __shared__ double red[kDirectThreads / 64];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        mx = fmax(mx, fabs(dP[i]));
+        if (zero) {
+            AJ[i] = 0.0;
+            AK[i] = 0.0;
         }
     }
+    const double pmax = block_max_direct(mx, red);   // also orders the zeroing before the scatter
+    double* Prow = (double*)smem_direct;             // [6][N]
+    double* Krow = Prow + 6 * N;                     // [6][N]
+    direct_class_rows<LA, LB, LC, LD, R>(g, md, it.chunk, it.nchunk, pmax, dP, AJ, AK, Prow, Krow);
 }
 
 // ---------------------------------------------------------------------------
@@ -671,6 +791,8 @@ static ks_status launch_all_classes(ks_batch* b)
 ks_status launch_eri(ks_batch* b)
 {
     KTimer tm(b, "eri");
+    // FP64 evaluation in both paths: evaluated in FP32, a 130-function
+    // molecule's SCF energy moved by 1.2e-4 Ha against the oracle
     if (b->opt.prec == KS_MIXED) return launch_all_classes<double, float>(b);
     return launch_all_classes<double, double>(b);
 }
@@ -716,7 +838,19 @@ ks_status launch_schwarz(ks_batch* b)
     return KS_OK;
 }
 
-template <typename A, bool GLOBAL>
+template <int LA, int LB, int LC, int LD, typename R>
+static ks_status launch_direct_rows(ks_batch* b, const DirectArgs& g, size_t lds, int zero)
+{
+    KS_HIP(hipFuncSetAttribute((const void*)direct_rows_kernel<LA, LB, LC, LD, R>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((direct_rows_kernel<LA, LB, LC, LD, R>), dim3((unsigned)b->jk_items.size()),
+                       dim3(kDirectThreads), lds, b->stream, g, zero);
+    KS_HIP(hipGetLastError());
+    return KS_OK;
+}
+
+// Integrals evaluated in R (the Boys table of that type), accumulated in A.
+template <typename A, typename R, bool GLOBAL>
 static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, bool incremental)
 {
     DirectArgs g;
@@ -732,6 +866,7 @@ static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, b
         g.Q[c] = b->d_Q[c];
     }
     g.tab = b->d_boys;
+    g.tabf = b->d_boys_f;
     g.P = P;
     g.Pref = incremental ? b->d_Pprev : nullptr;
     g.dP = b->d_work;
@@ -746,14 +881,26 @@ static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, b
     g.only_active = only_active;
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
-    const size_t lds = GLOBAL ? 0 : 3 * (size_t)maxn * maxn * sizeof(A);
-    KS_HIP(hipFuncSetAttribute((const void*)direct_jk_kernel<A, GLOBAL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
     KTimer tm(b, "jk_direct");
-    hipLaunchKernelGGL((direct_jk_kernel<A, GLOBAL>), dim3((unsigned)b->jk_items.size()), dim3(kDirectThreads), lds,
-                       b->stream, g);
-    KS_HIP(hipGetLastError());
-    return KS_OK;
+    if constexpr (GLOBAL) {
+        static_assert(std::is_same<A, double>::value, "global partials are FP64");
+        const size_t lds = 12 * (size_t)maxn * sizeof(double);
+        ks_status st;
+        if ((st = launch_direct_rows<0, 0, 0, 0, R>(b, g, lds, 1))) return st;
+        if ((st = launch_direct_rows<1, 0, 0, 0, R>(b, g, lds, 0))) return st;
+        if ((st = launch_direct_rows<1, 0, 1, 0, R>(b, g, lds, 0))) return st;
+        if ((st = launch_direct_rows<1, 1, 0, 0, R>(b, g, lds, 0))) return st;
+        if ((st = launch_direct_rows<1, 1, 1, 0, R>(b, g, lds, 0))) return st;
+        return launch_direct_rows<1, 1, 1, 1, R>(b, g, lds, 0);
+    } else {
+        const size_t lds = 3 * (size_t)maxn * maxn * sizeof(A);
+        KS_HIP(hipFuncSetAttribute((const void*)direct_jk_kernel<A, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        hipLaunchKernelGGL((direct_jk_kernel<A, R>), dim3((unsigned)b->jk_items.size()), dim3(kDirectThreads), lds,
+                           b->stream, g);
+        KS_HIP(hipGetLastError());
+        return KS_OK;
+    }
 }
 
 ks_status launch_direct_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,
@@ -765,9 +912,10 @@ ks_status launch_direct_jk(ks_batch* b, const double* P, double* J, double* K, b
     }
     const int mode = jk_mode(b);
     const bool f64 = mode != 1;
-    ks_status st = mode == 0 ? run_direct_jk<double, false>(b, P, only_active, incremental)
-                 : mode == 1 ? run_direct_jk<float, false>(b, P, only_active, incremental)
-                             : run_direct_jk<double, true>(b, P, only_active, incremental);
+    // integrals evaluated in FP64 in both paths (as in the stored build)
+    ks_status st = mode == 0 ? run_direct_jk<double, double, false>(b, P, only_active, incremental)
+                 : mode == 1 ? run_direct_jk<float, double, false>(b, P, only_active, incremental)
+                             : run_direct_jk<double, double, true>(b, P, only_active, incremental);
     if (st) return st;
     return launch_jk_reduce(b, f64, P, J, K, only_active, incremental, track);
 }

@@ -80,6 +80,32 @@ def test_eri_packed(small):
         assert np.abs(got - ref).max() < 1e-12, m
 
 
+def test_eri_mixed(ks):
+    # The mixed path evaluates the integrals in FP64, skips primitive quartets
+    # whose prefactor is below 1e-14 (at most 81 per contracted quartet, each
+    # bounded by its prefactor), and stores them in FP32 (half an ulp:
+    # 6e-8 |I|), so |dI| <= 1e-12 + 6e-8 |I|.
+    mols = _mols_small() + [molgen.tree(9, 1, 0)]
+    with ks.Batch(mols, prec=ks.KS_MIXED) as b:
+        b.eri_build()
+        for m, (z, x) in enumerate(mols):
+            o = O.Mol(z, x)
+            got = b.eri(m)
+            if m < len(mols) - 1:
+                ref = o.eri()
+                assert np.all(np.abs(got - ref) <= 1e-12 + 6e-8 * np.abs(ref)), m
+                continue
+            rng = np.random.default_rng(6)
+            N = o.nbf
+            for _ in range(2000):
+                i, j, k, l = (int(v) for v in rng.integers(0, N, 4))
+                ij = i * (i + 1) // 2 + j if i >= j else j * (j + 1) // 2 + i
+                kl = k * (k + 1) // 2 + l if k >= l else l * (l + 1) // 2 + k
+                idx = ij * (ij + 1) // 2 + kl if ij >= kl else kl * (kl + 1) // 2 + ij
+                ref = o.eri_one(i, j, k, l)
+                assert abs(got[idx] - ref) <= 1e-12 + 6e-8 * abs(ref), (i, j, k, l, got[idx], ref)
+
+
 def test_grid(small):
     mols, orc, b = small
     for m, o in enumerate(orc):
