@@ -494,7 +494,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         }
         if ((st = upload(b, &b->d_pair_ao[c], pao))) return st;
         if ((st = upload(b, &b->d_pairs[c], pairs[c]))) return st;
-        if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair * 5))) return st;
+        if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair * kPairFields))) return st;
         if ((st = dev_alloc(b, &b->d_Q[c], pairs[c].size()))) return st;
     }
     for (int c = 0; c < kNClass; c++)

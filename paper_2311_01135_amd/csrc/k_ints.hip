@@ -37,6 +37,19 @@ void build_boys_table(std::vector<double>& tab)
     }
 }
 
+// Reciprocal square root for x > 0: the hardware estimate refined by
+// Newton-Raphson steps y <- y (3 - x y^2) / 2, each of which roughly doubles
+// the number of correct bits (two for FP64; the FP32 estimate is ~1 ulp).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) { return __builtin_amdgcn_rsqf(x); }
+
 template <typename R> struct BoysOrder;
 template <> struct BoysOrder<double> { static constexpr int K = 7; };
 template <> struct BoysOrder<float> { static constexpr int K = 4; };
@@ -62,8 +75,9 @@ __device__ __forceinline__ void boys(R T, R (&F)[L + 1], const R* __restrict__ t
             for (int m = L - 1; m >= 0; --m) F[m] = (R(2) * T * F[m + 1] + e) * R(1.0 / (2 * m + 1));
         }
     } else {
-        R e = exp(-T), inv = R(1) / T;
-        F[0] = R(0.5) * sqrt(R(kPi) * inv);
+        const R rt = rsqrt_nr(T);
+        R e = exp(-T), inv = rt * rt;
+        F[0] = R(0.5 * 1.7724538509055160273) * rt;   // sqrt(pi) / 2 / sqrt(T)
 #pragma unroll
         for (int m = 0; m < L; ++m) F[m + 1] = (R(2 * m + 1) * F[m] - e) * R(0.5) * inv;
     }
@@ -155,24 +169,25 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
     for (int i = 0; i < NA * NB * NC * ND; i++) acc[i] = R(0);
     for (int ip = 0; ip < kNPrimPair; ip++) {
         const double bP[3] = {vb.get(1, ip), vb.get(2, ip), vb.get(3, ip)};
-        const R p = R(vb.get(0, ip)), Kb = R(vb.get(4, ip));
+        const R p = R(vb.get(0, ip)), Kb = R(vb.get(4, ip)), ipv = R(vb.get(5, ip));
         // negligible for every ket: q >= kQMin and |K_cd| <= kKMax bound the prefactor
-        if (fabs(Kb) * pi25 * R(kKMax) / (p * R(kQMin) * sqrt(p + R(kQMin))) < cut) continue;
+        if (fabs(Kb) * pi25 * R(kKMax / kQMin) * ipv * rsqrt_nr(p + R(kQMin)) < cut) continue;
         R eb[3][4][3];
-        const R i2p = R(0.5) / p;
+        const R i2p = R(0.5) * ipv;
 #pragma unroll
         for (int d = 0; d < 3; d++) hermite_E<R>(R(bP[d] - sa.A[d]), R(bP[d] - sb.A[d]), i2p, eb[d]);
         for (int jp = 0; jp < kNPrimPair; jp++) {
             const double kP[3] = {vk.get(1, jp), vk.get(2, jp), vk.get(3, jp)};
-            const R q = R(vk.get(0, jp)), Kk = R(vk.get(4, jp));
-            const R pref = pi25 / (p * q * sqrt(p + q)) * Kb * Kk;
+            const R q = R(vk.get(0, jp)), Kk = R(vk.get(4, jp)), iqv = R(vk.get(5, jp));
+            const R rs = rsqrt_nr(p + q);                 // 1/sqrt(p + q)
+            const R pref = pi25 * ipv * iqv * rs * Kb * Kk;
             if (fabs(pref) < cut) continue;
             R ek[3][4][3];
-            const R i2q = R(0.5) / q;
+            const R i2q = R(0.5) * iqv;
 #pragma unroll
             for (int d = 0; d < 3; d++) hermite_E<R>(R(kP[d] - sc.A[d]), R(kP[d] - sd.A[d]), i2q, ek[d]);
             const R PQx = R(bP[0] - kP[0]), PQy = R(bP[1] - kP[1]), PQz = R(bP[2] - kP[2]);
-            const R pq = p + q, alpha = p * q / pq;
+            const R alpha = p * q * (rs * rs);            // p q / (p + q)
             const R T = alpha * (PQx * PQx + PQy * PQy + PQz * PQz);
             R F[L + 1];
             boys<L, R>(T, F, tab);
@@ -336,6 +351,7 @@ __global__ void pair_kernel(const Shell* __restrict__ shells, const Pair* __rest
     }
     out[(size_t)k * npair + ip] = p;
     out[((size_t)4 * kNPrimPair + k) * npair + ip] = A.c[ka] * B.c[kb] * exp(-a * b / p * r2);
+    out[((size_t)5 * kNPrimPair + k) * npair + ip] = 1.0 / p;
 }
 
 // ---------------------------------------------------------------------------

@@ -58,8 +58,9 @@ struct Shell {
 };
 
 // Primitive-pair data of a shell pair (McMurchie-Davidson Gaussian product):
-// p = a + b, P = (a A + b B)/p, K = c_a c_b exp(-a b/p |A-B|^2), stored
-// field-major over the pairs of a pair class (see pair_kernel).
+// p = a + b, P = (a A + b B)/p, K = c_a c_b exp(-a b/p |A-B|^2) and 1/p,
+// stored field-major over the pairs of a pair class (see pair_kernel).
+constexpr int kPairFields = 6;   // p, Px, Py, Pz, K, 1/p
 
 // Shell pair (global shell indices); sa carries the higher angular momentum.
 struct Pair {
