@@ -84,6 +84,9 @@ typedef struct {
     double schwarz_tol;     /* Schwarz screening: stored path, skip quartets with Q_ab Q_cd below it (0 = off);
                                direct path, skip quartets with Q_ab Q_cd max|dP| below it (0 = 1e-12 FP64,
                                1e-10 mixed) */
+    int graphs;             /* 1: from the second SCF iteration on, scf_step / scf_solve replay one
+                               iteration's launches as a captured HIP graph (needs a non-NULL stream at
+                               ks_batch_create; ignored while kernel timing is on).  0 = plain launches */
 } ks_options;
 
 /* Initial density.  The paper only says C_1 is initialised (section 3.1).

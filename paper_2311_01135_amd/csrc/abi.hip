@@ -192,6 +192,47 @@ static ks_status upload(ks_batch* b, T** p, const std::vector<T>& v)
     return KS_OK;
 }
 
+// Integral-direct builds visit, for each bra, only the kets that pass the
+// density-weighted Schwarz test; with every molecule's pairs of a class in
+// decreasing order of Q (the same order for bras and kets), those kets form
+// a prefix of the bra's ket range.  Reorders the pair lists, their AO
+// offsets, Schwarz factors and primitive-pair tables once, after Q is known.
+ks_status ks::sort_pairs_by_schwarz(ks_batch* b)
+{
+    if (b->pairs_sorted) return KS_OK;
+    for (int c = 0; c < 3; c++) {
+        const long n = b->npairs[c];
+        if (!n) continue;
+        std::vector<double> Q(n);
+        KS_HIP(hipMemcpyAsync(Q.data(), b->d_Q[c], sizeof(double) * n, hipMemcpyDeviceToHost, b->stream));
+        KS_HIP(hipStreamSynchronize(b->stream));
+        std::vector<int> perm(n);
+        for (long k = 0; k < n; k++) perm[k] = (int)k;
+        for (const MolDesc& md : b->mol) {
+            auto first = perm.begin() + md.pair0[c];
+            std::stable_sort(first, first + md.npair[c], [&](int x, int y) { return Q[x] > Q[y]; });
+        }
+        int* d_perm;
+        Pair* pairs;
+        int2* pao;
+        double *pp, *Qn;
+        ks_status st;
+        if ((st = upload(b, &d_perm, perm))) return st;
+        if ((st = dev_alloc(b, &pairs, n))) return st;
+        if ((st = dev_alloc(b, &pao, n))) return st;
+        if ((st = dev_alloc(b, &pp, (size_t)n * kNPrimPair * kPairFields))) return st;
+        if ((st = dev_alloc(b, &Qn, n))) return st;
+        if ((st = launch_permute_pairs(b, c, d_perm, pairs, pao, pp, Qn))) return st;
+        KS_HIP(hipStreamSynchronize(b->stream));
+        b->d_pairs[c] = pairs;
+        b->d_pair_ao[c] = pao;
+        b->d_pp[c] = pp;
+        b->d_Q[c] = Qn;
+    }
+    b->pairs_sorted = true;
+    return KS_OK;
+}
+
 static void free_batch(ks_batch* b)
 {
     if (!b) return;
@@ -199,6 +240,7 @@ static void free_batch(ks_batch* b)
     resolve_timers(b);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     else (void)hipDeviceSynchronize();
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     for (void* p : b->allocs) (void)hipFree(p);
     if (b->ev_grid) (void)hipEventDestroy(b->ev_grid);
     if (b->ev_main) (void)hipEventDestroy(b->ev_main);
@@ -275,8 +317,8 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         set_error("unknown xc or precision option");
         return KS_EINVAL;
     }
-    if ((opt.direct != 0 && opt.direct != 1) || !(opt.schwarz_tol >= 0.0)) {
-        set_error("direct must be 0 or 1 and schwarz_tol >= 0");
+    if ((opt.direct != 0 && opt.direct != 1) || !(opt.schwarz_tol >= 0.0) || (opt.graphs != 0 && opt.graphs != 1)) {
+        set_error("direct and graphs must be 0 or 1 and schwarz_tol >= 0");
         return KS_EINVAL;
     }
     if (opt.guess != KS_GUESS_ATOM && opt.guess != KS_GUESS_CORE) {
@@ -461,6 +503,8 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     std::vector<double> tab, rad, ang, Zc(b->Z.begin(), b->Z.end());
     build_boys_table(tab);
     std::vector<float> tabf(tab.begin(), tab.end());
+    std::vector<double> boys_rows;
+    build_boys_rows(boys_rows);
     radial_rule(opt.n_rad, rad);
     gauss_legendre(opt.n_theta, ang);
     std::vector<long> ptoff;
@@ -480,6 +524,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     if ((st = upload(b, &b->d_Zc, Zc))) return st;
     if ((st = upload(b, &b->d_boys, tab))) return st;
     if ((st = upload(b, &b->d_boys_f, tabf))) return st;
+    if ((st = upload(b, &b->d_boys_rows, boys_rows))) return st;
     if ((st = upload(b, &b->d_radial, rad))) return st;
     if ((st = upload(b, &b->d_ang, ang))) return st;
     if ((st = upload(b, &b->d_ptoff, ptoff))) return st;
@@ -615,6 +660,7 @@ ks_status eri_build(ks_batch* b)
         if ((st = launch_schwarz(b))) return st;
     }
     if (b->opt.direct) {        // integral-direct: nothing is stored
+        if ((st = sort_pairs_by_schwarz(b))) return st;
         b->eri_done = true;
         return KS_OK;
     }
@@ -703,12 +749,11 @@ ks_status grid_wait(ks_batch* b)
 
 namespace ks {
 
-// One SCF iteration queued on the batch stream, without waiting: the count of
-// still-active molecules lands in pinned host memory (read by step_finish).
-ks_status step_launch(ks_batch* b)
+// The launches of one SCF iteration (every iteration issues the same ones
+// with the same arguments; the kernels skip retired molecules).
+static ks_status enqueue_iteration(ks_batch* b)
 {
     ks_status st;
-    if (!b->eri_done && (st = eri_build(b))) return st;
     // mixed and integral-direct paths: incremental J/K from P - Pprev
     const bool inc = b->opt.prec == KS_MIXED || b->opt.direct;
     if ((st = launch_jk(b, b->d_P, b->d_J, b->d_K, true, inc, true))) return st;
@@ -717,6 +762,48 @@ ks_status step_launch(ks_batch* b)
     if ((st = launch_iteration_tail(b))) return st;
     if ((st = launch_count_active(b))) return st;
     KS_HIP(hipMemcpyAsync(b->h_nactive, b->d_nactive, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    return KS_OK;
+}
+
+// One SCF iteration queued on the batch stream, without waiting: the count of
+// still-active molecules lands in pinned host memory (read by step_finish).
+// With options.graphs the second iteration is captured into a graph (the
+// first one also waits for the grid and may build the Schwarz order) and
+// every later one replays it.
+ks_status step_launch(ks_batch* b)
+{
+    ks_status st;
+    if (!b->eri_done && (st = eri_build(b))) return st;
+    const bool graph = b->opt.graphs && b->stream && !b->timing && b->iter >= 1 && !b->grid_pending;
+    if (graph && b->gexec) {
+        KS_HIP(hipGraphLaunch(b->gexec, b->stream));
+        b->iter++;
+        return KS_OK;
+    }
+    if (!graph) {
+        if ((st = enqueue_iteration(b))) return st;
+        b->iter++;
+        return KS_OK;
+    }
+    KS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue_iteration(b);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &gr);
+    if (!st && e != hipSuccess) {
+        set_error("graph capture of the SCF iteration failed: %s", hipGetErrorString(e));
+        st = KS_EDEVICE;
+    }
+    if (!st) {
+        const hipError_t ei = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+            b->gexec = nullptr;
+            st = KS_EDEVICE;
+        }
+    }
+    if (gr) (void)hipGraphDestroy(gr);
+    if (st) return st;
+    KS_HIP(hipGraphLaunch(b->gexec, b->stream));
     b->iter++;
     return KS_OK;
 }

@@ -33,12 +33,16 @@ void resolve_timers(ks_batch* b);
 
 // integrals (k_ints.hip)
 void build_boys_table(std::vector<double>& tab);
+void build_boys_rows(std::vector<double>& rows);
 ks_status launch_int1e(ks_batch* b);
 ks_status launch_pairs(ks_batch* b);
 ks_status launch_eri(ks_batch* b);
 ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out);
 // Schwarz factors Q_ab = max_component sqrt|(ab|ab)| of every shell pair.
 ks_status launch_schwarz(ks_batch* b);
+ks_status sort_pairs_by_schwarz(ks_batch* b);
+ks_status launch_permute_pairs(ks_batch* b, int c, const int* perm, Pair* pairs_out, int2* pao_out, double* pp_out,
+                               double* Q_out);
 // Integral-direct J/K: the ERIs of every quartet that survives the
 // density-weighted Schwarz test are computed and digested on the fly.
 ks_status launch_direct_jk(ks_batch* b, const double* P, double* J, double* K, bool only_active, bool incremental,

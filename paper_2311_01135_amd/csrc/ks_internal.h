@@ -43,6 +43,13 @@ constexpr double kBoysDT = 0.05;
 constexpr double kBoysTMax = 36.0;
 constexpr int kBoysNT = 722;
 constexpr int kBoysM = 12;
+// Row table for the ERI kernels, small enough for LDS: for each total
+// angular momentum L <= 4, row i holds F_L..F_{L+7} at T_i = i * kBoysDTR
+// (eight values: a 64-byte row read with four 16-byte loads).
+constexpr double kBoysDTR = 0.1;
+constexpr int kBoysNTR = 361;
+constexpr int kBoysKR = 8;
+constexpr int kBoysLR = 5;
 
 // A contracted shell: 2s and 2p of a heavy atom are separate shells that
 // share exponents.  c[] already holds contraction x primitive normalisation
@@ -130,6 +137,7 @@ struct ks_batch {
     hipStream_t aux = nullptr;
     hipEvent_t ev_main = nullptr, ev_grid = nullptr;
     bool grid_pending = false;
+    hipGraphExec_t gexec = nullptr; // captured SCF iteration (options.graphs)
     int n_mol = 0;
     int max_np = 0;
     int max_nshell = 0;
@@ -158,9 +166,11 @@ struct ks_batch {
     double* d_pp[3] = {nullptr, nullptr, nullptr};   // [5][9][npair] primitive-pair tables
     double* d_Q[3] = {nullptr, nullptr, nullptr};    // Schwarz factors max sqrt|(ab|ab)| per pair
     bool schwarz_done = false;
+    bool pairs_sorted = false;      // pairs in decreasing Schwarz order (integral-direct builds)
     long* d_qoff[ks::kNClass] = {};  // prefix over molecules (n_mol + 1)
     void* d_eri[ks::kNClass] = {};   // component-major, FP64 or FP32
     double* d_boys = nullptr;
+    double* d_boys_rows = nullptr;  // [kBoysLR][kBoysNTR][kBoysKR]
     float* d_boys_f = nullptr;
     double* d_radial = nullptr;     // r_i, w_i (n_rad each)
     double* d_ang = nullptr;        // cos theta_j, w_j (n_theta each)

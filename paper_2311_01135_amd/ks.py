@@ -44,7 +44,8 @@ class Options(C.Structure):
                 ("n_phi", C.c_int), ("e_tol", C.c_double), ("comm_tol", C.c_double),
                 ("max_iter", C.c_int), ("diis_space", C.c_int), ("jk_chunks", C.c_int),
                 ("xc_chunks", C.c_int), ("guess", C.c_int), ("xc_points", C.c_int),
-                ("xc_waves", C.c_int), ("direct", C.c_int), ("schwarz_tol", C.c_double)]
+                ("xc_waves", C.c_int), ("direct", C.c_int), ("schwarz_tol", C.c_double),
+                ("graphs", C.c_int)]
 
 
 _lib = None

@@ -74,6 +74,8 @@ def test_rejects_bad_options(lib):
     assert st == -1 and "direct" in err
     st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], schwarz_tol=-1.0)
     assert st == -1 and "schwarz_tol" in err
+    st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], graphs=3)
+    assert st == -1 and "graphs" in err
 
 
 def test_rejects_too_large_fp64(lib):
