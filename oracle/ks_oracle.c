@@ -19,6 +19,9 @@
  * Textbook pieces the paper cites but does not print:
  *   STO-3G (Hehre, Stewart, Pople 1969): universal zeta=1 expansions scaled
  *     by zeta^2;
+ *   6-31G (Hehre, Ditchfield, Pople 1972; H from the 31G set), H, C, N, O:
+ *     a six-primitive core s shell and a 3 + 1 split valence (sp shells
+ *     sharing exponents);
  *   Obara-Saika recurrences (J. Chem. Phys. 84, 3963 (1986)) for S, T, V
  *     and the ERIs (vertical recurrence + horizontal transfer);
  *   Boys function: F0 = 1/2 sqrt(pi/T) erf(sqrt T); F_m by series + downward
@@ -53,6 +56,31 @@ static const double STO2SP_A[3] = {0.9942027, 0.2310313, 0.0751386};
 static const double STO2S_D[3] = {-0.09996723, 0.39951283, 0.70011547};
 static const double STO2P_D[3] = {0.15591627, 0.60768372, 0.39195739};
 
+/* ------------------------------------------------------------------ */
+/* 6-31G: per element the core 1s (6), inner valence sp (3) and outer  */
+/* valence sp (1) shells; H: 31G (3 + 1).  Exponents, s and p          */
+/* contraction coefficients.                                           */
+/* ------------------------------------------------------------------ */
+typedef struct { double a[6], d[6]; } g1s_t;
+typedef struct { double a[3], ds[3], dp[3]; double a3; } gsp_t;
+static const g1s_t G631_1S[3] = {   /* C, N, O */
+    {{3047.5249, 457.36951, 103.94869, 29.210155, 9.2866630, 3.1639270},
+     {0.0018347, 0.0140373, 0.0688426, 0.2321844, 0.4679413, 0.3623120}},
+    {{4173.5110, 627.45790, 142.90210, 40.234330, 12.820210, 4.3904370},
+     {0.0018348, 0.0139950, 0.0685870, 0.2322410, 0.4690700, 0.3604550}},
+    {{5484.6717, 825.23495, 188.04696, 52.964500, 16.897570, 5.7996353},
+     {0.0018311, 0.0139501, 0.0684451, 0.2327143, 0.4701930, 0.3585209}}};
+static const gsp_t G631_SP[3] = {
+    {{7.8682724, 1.8812885, 0.5442493}, {-0.1193324, -0.1608542, 1.1434564}, {0.0689991, 0.3164240, 0.7443083},
+     0.1687144},
+    {{11.626358, 2.7162800, 0.7722180}, {-0.1149610, -0.1691180, 1.1458520}, {0.0675800, 0.3239070, 0.7408950},
+     0.2120313},
+    {{15.539616, 3.5999336, 1.0137618}, {-0.1107775, -0.1480263, 1.1307670}, {0.0708743, 0.3397528, 0.7271586},
+     0.2700058}};
+static const double G631_H_A[3] = {18.7311370, 2.8253937, 0.6401217};
+static const double G631_H_D[3] = {0.03349460, 0.23472695, 0.81375733};
+static const double G631_H_A2 = 0.1612778;
+
 static int zeta_of(int Z, double *z1, double *z2)
 {
     switch (Z) {
@@ -71,8 +99,9 @@ typedef struct {
     int bf0;        /* first AO index */
     int np;         /* primitives */
     double A[3];
-    double a[3];
-    double c[3];    /* contraction coefficient x primitive norm x renorm */
+    double a[6];
+    double c[6];    /* contraction coefficient x primitive norm x renorm */
+    double occ;     /* initial-guess occupation per function of the shell */
 } oshell;
 
 typedef struct {
@@ -118,28 +147,35 @@ static double prim_norm(int L, double a)
     return L == 0 ? n : n * 2.0 * sqrt(a);
 }
 
-static void add_shell(omol *m, int *ns, int atom, int L, const double *a0, double zeta,
-                      const double *d, int bf0)
+/* np primitives with exponents a0[k] * zeta^2 and contraction coefficients d */
+static void add_shell_n(omol *m, int *ns, int atom, int L, int np, const double *a0, double zeta,
+                        const double *d, int bf0)
 {
     oshell *s = &m->sh[*ns];
     int k, l;
     double self = 0.0;
-    s->L = L; s->atom = atom; s->bf0 = bf0; s->np = 3;
+    s->L = L; s->atom = atom; s->bf0 = bf0; s->np = np;
     for (k = 0; k < 3; k++) s->A[k] = m->R[3 * atom + k];
-    for (k = 0; k < 3; k++) {
+    for (k = 0; k < np; k++) {
         s->a[k] = a0[k] * zeta * zeta;
         s->c[k] = d[k] * prim_norm(L, s->a[k]);
     }
     /* renormalise so that <phi|phi> = 1 (x component for p) */
-    for (k = 0; k < 3; k++)
-        for (l = 0; l < 3; l++) {
+    for (k = 0; k < np; k++)
+        for (l = 0; l < np; l++) {
             double p = s->a[k] + s->a[l];
             double v = pow(ORC_PI / p, 1.5);
             if (L == 1) v *= 0.5 / p;
             self += s->c[k] * s->c[l] * v;
         }
-    for (k = 0; k < 3; k++) s->c[k] /= sqrt(self);
+    for (k = 0; k < np; k++) s->c[k] /= sqrt(self);
     (*ns)++;
+}
+
+static void add_shell(omol *m, int *ns, int atom, int L, const double *a0, double zeta,
+                      const double *d, int bf0)
+{
+    add_shell_n(m, ns, atom, L, 3, a0, zeta, d, bf0);
 }
 
 void orc_mol_free(void *h)
@@ -150,19 +186,29 @@ void orc_mol_free(void *h)
     free(m);
 }
 
+/* index of a 6-31G heavy element in the tables (C, N, O), -1 otherwise */
+static int g631_index(int Z) { return Z == 6 ? 0 : (Z == 7 ? 1 : (Z == 8 ? 2 : -1)); }
+
 /* Returns NULL for unsupported elements, odd electron count, non-finite or
- * coincident (< 0.1 bohr) atoms. */
-void *orc_mol_new(int natom, const int *Z, const double *xyz_ang, int charge)
+ * coincident (< 0.1 bohr) atoms.  basis: 0 = STO-3G (H, C, N, O, F),
+ * 1 = 6-31G (H, C, N, O). */
+void *orc_mol_new_basis(int natom, const int *Z, const double *xyz_ang, int charge, int basis)
 {
     omol *m;
     int i, j, nsh = 0, nbf = 0, ns = 0, ne = 0;
-    if (natom <= 0) return NULL;
+    if (natom <= 0 || basis < 0 || basis > 1) return NULL;
     for (i = 0; i < natom; i++) {
         double z1 = 0.0, z2 = 0.0;
         if (!zeta_of(Z[i], &z1, &z2)) return NULL;
+        if (basis == 1 && Z[i] != 1 && g631_index(Z[i]) < 0) return NULL;
         for (j = 0; j < 3; j++) if (!isfinite(xyz_ang[3 * i + j])) return NULL;
-        nsh += Z[i] == 1 ? 1 : 3;
-        nbf += Z[i] == 1 ? 1 : 5;
+        if (basis == 0) {
+            nsh += Z[i] == 1 ? 1 : 3;
+            nbf += Z[i] == 1 ? 1 : 5;
+        } else {
+            nsh += Z[i] == 1 ? 2 : 5;
+            nbf += Z[i] == 1 ? 2 : 9;
+        }
         ne += Z[i];
     }
     ne -= charge;
@@ -187,11 +233,34 @@ void *orc_mol_new(int natom, const int *Z, const double *xyz_ang, int charge)
     nbf = 0;
     for (i = 0; i < natom; i++) {
         double z1 = 0.0, z2 = 0.0;
+        const double one = 1.0;
+        const int ns0 = ns;
         zeta_of(Z[i], &z1, &z2);
-        add_shell(m, &ns, i, 0, STO1S_A, z1, STO1S_D, nbf); nbf += 1;
-        if (Z[i] > 1) {
-            add_shell(m, &ns, i, 0, STO2SP_A, z2, STO2S_D, nbf); nbf += 1;
-            add_shell(m, &ns, i, 1, STO2SP_A, z2, STO2P_D, nbf); nbf += 3;
+        if (basis == 0) {
+            add_shell(m, &ns, i, 0, STO1S_A, z1, STO1S_D, nbf); nbf += 1;
+            if (Z[i] > 1) {
+                add_shell(m, &ns, i, 0, STO2SP_A, z2, STO2S_D, nbf); nbf += 1;
+                add_shell(m, &ns, i, 1, STO2SP_A, z2, STO2P_D, nbf); nbf += 3;
+            }
+            /* neutral-atom occupations: H 1s 1; 1s 2, 2s 2, 2p (Z-4)/3 each */
+            m->sh[ns0].occ = Z[i] == 1 ? 1.0 : 2.0;
+            if (Z[i] > 1) { m->sh[ns0 + 1].occ = 2.0; m->sh[ns0 + 2].occ = (Z[i] - 4) / 3.0; }
+        } else if (Z[i] == 1) {
+            add_shell_n(m, &ns, i, 0, 3, G631_H_A, 1.0, G631_H_D, nbf); nbf += 1;
+            add_shell_n(m, &ns, i, 0, 1, &G631_H_A2, 1.0, &one, nbf); nbf += 1;
+            /* the valence electron split evenly over the inner and outer s */
+            m->sh[ns0].occ = 0.5; m->sh[ns0 + 1].occ = 0.5;
+        } else {
+            const int e = g631_index(Z[i]);
+            add_shell_n(m, &ns, i, 0, 6, G631_1S[e].a, 1.0, G631_1S[e].d, nbf); nbf += 1;
+            add_shell_n(m, &ns, i, 0, 3, G631_SP[e].a, 1.0, G631_SP[e].ds, nbf); nbf += 1;
+            add_shell_n(m, &ns, i, 1, 3, G631_SP[e].a, 1.0, G631_SP[e].dp, nbf); nbf += 3;
+            add_shell_n(m, &ns, i, 0, 1, &G631_SP[e].a3, 1.0, &one, nbf); nbf += 1;
+            add_shell_n(m, &ns, i, 1, 1, &G631_SP[e].a3, 1.0, &one, nbf); nbf += 3;
+            /* 1s 2; the valence split evenly over the inner and outer shells */
+            m->sh[ns0].occ = 2.0;
+            m->sh[ns0 + 1].occ = 1.0; m->sh[ns0 + 3].occ = 1.0;
+            m->sh[ns0 + 2].occ = (Z[i] - 4) / 6.0; m->sh[ns0 + 4].occ = (Z[i] - 4) / 6.0;
         }
     }
     for (i = 0; i < nsh; i++) {
@@ -209,13 +278,22 @@ int orc_mol_info(void *h, int *nbf, int *nocc, int *nshell)
     return 0;
 }
 
-/* Per-shell data for inspection: L, atom, bf0, exponents[3], coefs[3]. */
-void orc_shell(void *h, int s, int *L, int *atom, int *bf0, double *a, double *c)
+void *orc_mol_new(int natom, const int *Z, const double *xyz_ang, int charge)
+{
+    return orc_mol_new_basis(natom, Z, xyz_ang, charge, 0);
+}
+
+/* Per-shell data for inspection: L, atom, bf0, primitive count, exponents[6],
+ * coefs[6] (entries beyond the count are 0). */
+void orc_shell(void *h, int s, int *L, int *atom, int *bf0, int *np, double *a, double *c)
 {
     omol *m = (omol *)h;
     int k;
-    *L = m->sh[s].L; *atom = m->sh[s].atom; *bf0 = m->sh[s].bf0;
-    for (k = 0; k < 3; k++) { a[k] = m->sh[s].a[k]; c[k] = m->sh[s].c[k]; }
+    *L = m->sh[s].L; *atom = m->sh[s].atom; *bf0 = m->sh[s].bf0; *np = m->sh[s].np;
+    for (k = 0; k < 6; k++) {
+        a[k] = k < m->sh[s].np ? m->sh[s].a[k] : 0.0;
+        c[k] = k < m->sh[s].np ? m->sh[s].c[k] : 0.0;
+    }
 }
 
 double orc_enuc(void *h)
@@ -1102,8 +1180,9 @@ int orc_scf(void *h, int xc, int nrad, int nth, int nph, double e_tol, double co
         }
     /* initial density (the paper's "initialise C_1" leaves the choice open):
      * guess 0: diagonal superposition of neutral-atom ground-state
-     * occupations (H 1s 1; C/N/O/F 1s 2, 2s 2, 2p (Z-4)/3 each), scaled to
-     * N_e, used as rho_1 directly;  guess 1: core Hamiltonian -- diagonalise
+     * occupations (STO-3G: H 1s 1; C/N/O/F 1s 2, 2s 2, 2p (Z-4)/3 each;
+     * 6-31G: the valence occupation split evenly over the inner and outer
+     * shells), scaled to N_e, used as rho_1 directly;  guess 1: core Hamiltonian -- diagonalise
      * X^T H X at iteration 0. */
     memcpy(F, H, sizeof(double) * NN);
     it = 0;
@@ -1111,9 +1190,8 @@ int orc_scf(void *h, int xc, int nrad, int nth, int nph, double e_tol, double co
         double tot = 0.0;
         for (i = 0; i < m->nshell; i++) {
             const oshell *s = &m->sh[i];
-            int Z = m->Z[s->atom], c;
-            double occ = (Z == 1) ? 1.0 : (s->L == 1 ? (Z - 4) / 3.0 : 2.0);
-            for (c = 0; c < (s->L ? 3 : 1); c++) P[(s->bf0 + c) * N + s->bf0 + c] = occ;
+            int c;
+            for (c = 0; c < (s->L ? 3 : 1); c++) P[(s->bf0 + c) * N + s->bf0 + c] = s->occ;
         }
         for (i = 0; i < N; i++) tot += P[i * N + i];
         for (i = 0; i < N; i++) P[i * N + i] *= m->nelec / tot;

@@ -19,6 +19,7 @@ _LIB = os.path.join(_HERE, "libks_oracle.so")
 XC_HF, XC_B3LYP, XC_B3LYP5 = 0, 1, 2
 ST_CONVERGED, ST_MAXITER, ST_DIVERGED, ST_INVALID = 1, 2, 3, 4
 GUESS_ATOM, GUESS_CORE = 0, 1
+BASIS_STO3G, BASIS_631G = 0, 1
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -42,10 +43,12 @@ def lib():
         L = C.CDLL(build())
         L.orc_mol_new.restype = C.c_void_p
         L.orc_mol_new.argtypes = [C.c_int, _ip, _dp, C.c_int]
+        L.orc_mol_new_basis.restype = C.c_void_p
+        L.orc_mol_new_basis.argtypes = [C.c_int, _ip, _dp, C.c_int, C.c_int]
         L.orc_mol_free.argtypes = [C.c_void_p]
         L.orc_mol_info.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_shell.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                C.POINTER(C.c_int), _dp, _dp]
+                                C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _dp]
         L.orc_enuc.restype = C.c_double
         L.orc_enuc.argtypes = [C.c_void_p]
         L.orc_int1e.argtypes = [C.c_void_p, _dp, _dp, _dp]
@@ -111,10 +114,10 @@ def eigh(A):
 class Mol:
     """One molecule in the oracle: Z (ints), xyz in Angstrom."""
 
-    def __init__(self, Z, xyz_ang, charge: int = 0):
+    def __init__(self, Z, xyz_ang, charge: int = 0, basis: int = 0):
         Z = np.ascontiguousarray(Z, dtype=np.int32)
         xyz = np.ascontiguousarray(np.asarray(xyz_ang, dtype=np.float64).reshape(-1))
-        self.h = lib().orc_mol_new(len(Z), Z, xyz, charge)
+        self.h = lib().orc_mol_new_basis(len(Z), Z, xyz, charge, basis)
         if not self.h:
             raise ValueError("oracle rejected the molecule (element, charge or geometry)")
         nbf, nocc, nsh = C.c_int(), C.c_int(), C.c_int()
@@ -128,10 +131,11 @@ class Mol:
             self.h = None
 
     def shell(self, s):
-        L, at, b0 = C.c_int(), C.c_int(), C.c_int()
-        a, c = np.zeros(3), np.zeros(3)
-        lib().orc_shell(self.h, s, C.byref(L), C.byref(at), C.byref(b0), a, c)
-        return L.value, at.value, b0.value, a, c
+        """(L, atom, first AO, exponents, coefficients) of shell s."""
+        L, at, b0, n = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        a, c = np.zeros(6), np.zeros(6)
+        lib().orc_shell(self.h, s, C.byref(L), C.byref(at), C.byref(b0), C.byref(n), a, c)
+        return L.value, at.value, b0.value, a[:n.value].copy(), c[:n.value].copy()
 
     def enuc(self) -> float:
         return lib().orc_enuc(self.h)
