@@ -84,6 +84,7 @@ typedef struct {
     double schwarz_tol;     /* Schwarz screening: stored path, skip quartets with Q_ab Q_cd below it (0 = off);
                                direct path, skip quartets with Q_ab Q_cd max|dP| below it (0 = 1e-12 FP64,
                                1e-10 mixed) */
+    int basis;              /* KS_BASIS_STO3G (H, C, N, O, F) or KS_BASIS_631G (H, C, N, O) */
     int graphs;             /* 1: from the second SCF iteration on, scf_step / scf_solve replay one
                                iteration's launches as a captured HIP graph (needs a non-NULL stream at
                                ks_batch_create; ignored while kernel timing is on).  0 = plain launches */
@@ -95,6 +96,14 @@ typedef struct {
  * the first density.  KS_GUESS_CORE: orbitals of the core Hamiltonian. */
 #define KS_GUESS_ATOM 0
 #define KS_GUESS_CORE 1
+
+/* Basis sets (paper section 4: STO-3G for the generated data; 6-31G is the
+ * larger basis it also supports).  6-31G: six-primitive core s, 3 + 1 split
+ * valence with sp shells sharing exponents (9 functions per C/N/O, 2 per
+ * H); the initial density splits each atom's valence occupation evenly over
+ * the inner and outer shells. */
+#define KS_BASIS_STO3G 0
+#define KS_BASIS_631G 1
 
 /* Fills *o with the defaults: B3LYP, FP64, 50 x 12 x 24 grid, e_tol 1e-9,
  * comm_tol 1e-7, max_iter 100, diis_space 8, automatic chunking, atomic

@@ -89,22 +89,90 @@ static bool element_zetas(int Z, double& z1s, double& z2sp)
     }
 }
 
-// contraction coefficients x primitive norms, renormalised so <phi|phi> = 1
-static void make_shell(Shell& s, int L, const double* a0, double zeta, const double* d)
+// 6-31G (Hehre, Ditchfield, Pople 1972; H: the 31G set), H, C, N, O: per
+// heavy element a six-primitive 1s, an sp shell of three primitives (s and p
+// coefficients on shared exponents) and a one-primitive outer sp shell.
+struct G631Heavy {
+    double a1s[6], d1s[6];
+    double asp[3], ds[3], dp[3];
+    double aout;
+};
+static const G631Heavy kG631[3] = {   // C, N, O
+    {{3047.5249, 457.36951, 103.94869, 29.210155, 9.2866630, 3.1639270},
+     {0.0018347, 0.0140373, 0.0688426, 0.2321844, 0.4679413, 0.3623120},
+     {7.8682724, 1.8812885, 0.5442493}, {-0.1193324, -0.1608542, 1.1434564}, {0.0689991, 0.3164240, 0.7443083},
+     0.1687144},
+    {{4173.5110, 627.45790, 142.90210, 40.234330, 12.820210, 4.3904370},
+     {0.0018348, 0.0139950, 0.0685870, 0.2322410, 0.4690700, 0.3604550},
+     {11.626358, 2.7162800, 0.7722180}, {-0.1149610, -0.1691180, 1.1458520}, {0.0675800, 0.3239070, 0.7408950},
+     0.2120313},
+    {{5484.6717, 825.23495, 188.04696, 52.964500, 16.897570, 5.7996353},
+     {0.0018311, 0.0139501, 0.0684451, 0.2327143, 0.4701930, 0.3585209},
+     {15.539616, 3.5999336, 1.0137618}, {-0.1107775, -0.1480263, 1.1307670}, {0.0708743, 0.3397528, 0.7271586},
+     0.2700058}};
+static const double kG631H_a[3] = {18.7311370, 2.8253937, 0.6401217};
+static const double kG631H_d[3] = {0.03349460, 0.23472695, 0.81375733};
+static const double kG631H_aout = 0.1612778;
+
+static int g631_heavy(int Z) { return Z == 6 ? 0 : (Z == 7 ? 1 : (Z == 8 ? 2 : -1)); }
+
+// n primitives a0[k] zeta^2 with coefficients d[k] x primitive norms,
+// renormalised so <phi|phi> = 1
+static void make_shell(Shell& s, int L, int n, const double* a0, double zeta, const double* d)
 {
     s.L = L;
-    for (int k = 0; k < 3; k++) {
+    s.np = n;
+    for (int k = 0; k < kPrimMax; k++) s.a[k] = s.c[k] = 0.0;
+    for (int k = 0; k < n; k++) {
         s.a[k] = a0[k] * zeta * zeta;
-        const double n = std::pow(2.0 * s.a[k] / kPi, 0.75) * (L ? 2.0 * std::sqrt(s.a[k]) : 1.0);
-        s.c[k] = d[k] * n;
+        const double nk = std::pow(2.0 * s.a[k] / kPi, 0.75) * (L ? 2.0 * std::sqrt(s.a[k]) : 1.0);
+        s.c[k] = d[k] * nk;
     }
     double norm = 0.0;
-    for (int k = 0; k < 3; k++)
-        for (int l = 0; l < 3; l++) {
+    for (int k = 0; k < n; k++)
+        for (int l = 0; l < n; l++) {
             const double p = s.a[k] + s.a[l];
             norm += s.c[k] * s.c[l] * std::pow(kPi / p, 1.5) * (L ? 0.5 / p : 1.0);
         }
-    for (int k = 0; k < 3; k++) s.c[k] /= std::sqrt(norm);
+    for (int k = 0; k < n; k++) s.c[k] /= std::sqrt(norm);
+}
+
+// Appends the shells of one atom (position already in s.A, s.atom set);
+// returns the number of functions added.  Guess occupations per function:
+// STO-3G H 1s 1, heavy 1s 2, 2s 2, 2p (Z-4)/3; 6-31G the valence occupation
+// split evenly over the inner and outer shells.
+static int add_atom_shells(std::vector<Shell>& out, Shell s, int z, int basis, int nbf)
+{
+    const Sto3g sto;
+    const int first = nbf;
+    auto push = [&](int L, int n, const double* a0, double zeta, const double* d, double occ) {
+        make_shell(s, L, n, a0, zeta, d);
+        s.occ = occ;
+        s.ao = nbf;
+        out.push_back(s);
+        nbf += L ? 3 : 1;
+    };
+    const double one = 1.0;
+    if (basis == KS_BASIS_STO3G) {
+        double z1, z2;
+        element_zetas(z, z1, z2);
+        push(0, 3, sto.a1s, z1, sto.d1s, z == 1 ? 1.0 : 2.0);
+        if (z > 1) {
+            push(0, 3, sto.a2sp, z2, sto.d2s, 2.0);
+            push(1, 3, sto.a2sp, z2, sto.d2p, (z - 4) / 3.0);
+        }
+    } else if (z == 1) {
+        push(0, 3, kG631H_a, 1.0, kG631H_d, 0.5);
+        push(0, 1, &kG631H_aout, 1.0, &one, 0.5);
+    } else {
+        const G631Heavy& e = kG631[g631_heavy(z)];
+        push(0, 6, e.a1s, 1.0, e.d1s, 2.0);
+        push(0, 3, e.asp, 1.0, e.ds, 1.0);
+        push(1, 3, e.asp, 1.0, e.dp, (z - 4) / 6.0);
+        push(0, 1, &e.aout, 1.0, &one, 1.0);
+        push(1, 1, &e.aout, 1.0, &one, (z - 4) / 6.0);
+    }
+    return nbf - first;
 }
 
 // Treutler-Ahlrichs M4 (xi = 1, alpha = 0.6) on Chebyshev nodes of the 2nd kind:
@@ -220,7 +288,7 @@ ks_status ks::sort_pairs_by_schwarz(ks_batch* b)
         if ((st = upload(b, &d_perm, perm))) return st;
         if ((st = dev_alloc(b, &pairs, n))) return st;
         if ((st = dev_alloc(b, &pao, n))) return st;
-        if ((st = dev_alloc(b, &pp, (size_t)n * kNPrimPair * kPairFields))) return st;
+        if ((st = dev_alloc(b, &pp, (size_t)n * b->pp * kPairFields))) return st;
         if ((st = dev_alloc(b, &Qn, n))) return st;
         if ((st = launch_permute_pairs(b, c, d_perm, pairs, pao, pp, Qn))) return st;
         KS_HIP(hipStreamSynchronize(b->stream));
@@ -321,6 +389,10 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         set_error("direct and graphs must be 0 or 1 and schwarz_tol >= 0");
         return KS_EINVAL;
     }
+    if (opt.basis != KS_BASIS_STO3G && opt.basis != KS_BASIS_631G) {
+        set_error("basis must be KS_BASIS_STO3G or KS_BASIS_631G");
+        return KS_EINVAL;
+    }
     if (opt.guess != KS_GUESS_ATOM && opt.guess != KS_GUESS_CORE) {
         set_error("unknown guess option %d", opt.guess);
         return KS_EINVAL;
@@ -339,7 +411,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     b->n_mol = n_mol;
     b->a0 = opt.xc == KS_XC_HF ? 1.0 : 0.20;
     const int maxn = opt.prec == KS_MIXED ? kMaxNbf : 82;
-    Sto3g sto;
+    b->pp = opt.basis == KS_BASIS_631G ? kPrimPairMax : kNPrimPair;
 
     long atom0 = 0, mat0 = 0, grid0 = 0, ao0 = 0;
     long qoff[kNClass] = {0, 0, 0, 0, 0, 0};
@@ -364,8 +436,9 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         for (int a = 0; a < na; a++) {
             const int z = Zin[atom0 + a];
             double z1, z2;
-            if (!element_zetas(z, z1, z2)) {
-                set_error("molecule %d atom %d: element Z=%d is not in {H, C, N, O, F}", m, a, z);
+            if (!element_zetas(z, z1, z2) || (opt.basis == KS_BASIS_631G && z != 1 && g631_heavy(z) < 0)) {
+                set_error("molecule %d atom %d: element Z=%d is not in %s", m, a, z,
+                          opt.basis == KS_BASIS_631G ? "{H, C, N, O} (6-31G)" : "{H, C, N, O, F}");
                 return KS_EINVAL;
             }
             double p[3];
@@ -391,20 +464,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
             Shell s{};
             for (int k = 0; k < 3; k++) s.A[k] = p[k];
             s.atom = a;
-            make_shell(s, 0, sto.a1s, z1, sto.d1s);
-            s.ao = nbf;
-            b->shells.push_back(s);
-            nbf += 1;
-            if (z > 1) {
-                make_shell(s, 0, sto.a2sp, z2, sto.d2s);
-                s.ao = nbf;
-                b->shells.push_back(s);
-                nbf += 1;
-                make_shell(s, 1, sto.a2sp, z2, sto.d2p);
-                s.ao = nbf;
-                b->shells.push_back(s);
-                nbf += 3;
-            }
+            nbf += add_atom_shells(b->shells, s, z, opt.basis, nbf);
         }
         if (ne <= 0 || (ne & 1)) {
             set_error("molecule %d: %d electrons; the restricted method needs a positive even count", m, ne);
@@ -460,7 +520,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
             md.q0[c] = qoff[c];
             qoff[c] += md.nq[c];
             qprefix[c].push_back(qoff[c]);
-            b->nprimq += md.nq[c] * kNPrimPair * kNPrimPair;
+            b->nprimq += md.nq[c] * (long)b->pp * b->pp;
         }
         atom0 += na;
         mat0 += (long)nbf * nbf;
@@ -539,7 +599,7 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         }
         if ((st = upload(b, &b->d_pair_ao[c], pao))) return st;
         if ((st = upload(b, &b->d_pairs[c], pairs[c]))) return st;
-        if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * kNPrimPair * kPairFields))) return st;
+        if ((st = dev_alloc(b, &b->d_pp[c], pairs[c].size() * (size_t)b->pp * kPairFields))) return st;
         if ((st = dev_alloc(b, &b->d_Q[c], pairs[c].size()))) return st;
     }
     for (int c = 0; c < kNClass; c++)

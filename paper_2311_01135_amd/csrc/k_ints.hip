@@ -204,12 +204,15 @@ __device__ __forceinline__ void hermite_E(R XPA, R XPB, R i2p, R (&e)[4][3])
 // Cartesian exponent of component c (0..2 for p, s has 0) along direction d.
 __host__ __device__ constexpr int lexp(int L, int c, int d) { return (L == 1 && c == d) ? 1 : 0; }
 
-// Read-only view of one pair in a field-major primitive-pair table.
+// Read-only view of one pair in a field-major primitive-pair table with PP
+// primitive pairs per shell pair (9 for STO-3G; 36 for 6-31G, padded with
+// zero-weight pairs where a shell has fewer than six primitives).
+template <int PP = kNPrimPair>
 struct PairView {
     const double* t;
     long n;
     int i;
-    __device__ __forceinline__ double get(int f, int k) const { return t[((size_t)f * kNPrimPair + k) * n + i]; }
+    __device__ __forceinline__ double get(int f, int k) const { return t[((size_t)f * PP + k) * n + i]; }
 };
 
 // ---------------------------------------------------------------------------
@@ -219,31 +222,31 @@ struct PairView {
 // ---------------------------------------------------------------------------
 // ROWS: tab is the Boys row table of L = LA + LB + LC + LD (boys_rows), else
 // the full table (boys).
-template <int LA, int LB, int LC, int LD, typename R, bool ROWS = false>
+template <int LA, int LB, int LC, int LD, typename R, bool ROWS = false, int PP = kNPrimPair>
 __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, const Shell& sc, const Shell& sd,
-                                            const PairView& vb, const PairView& vk, const R* __restrict__ tab, R cut,
-                                            R* acc)
+                                            const PairView<PP>& vb, const PairView<PP>& vk, const R* __restrict__ tab,
+                                            R cut, R* acc)
 {
     constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     const R pi25 = R(2.0 * 17.493418327624862);   // 2 pi^(5/2)
 #pragma unroll
     for (int i = 0; i < NA * NB * NC * ND; i++) acc[i] = R(0);
-    for (int ip = 0; ip < kNPrimPair; ip++) {
+    auto bra = [&](int ip) {
         const double bP[3] = {vb.get(1, ip), vb.get(2, ip), vb.get(3, ip)};
         const R p = R(vb.get(0, ip)), Kb = R(vb.get(4, ip)), ipv = R(vb.get(5, ip));
         // negligible for every ket: q >= kQMin and |K_cd| <= kKMax bound the prefactor
-        if (fabs(Kb) * pi25 * R(kKMax / kQMin) * ipv * rsqrt_nr(p + R(kQMin)) < cut) continue;
+        if (fabs(Kb) * pi25 * R(kKMax / kQMin) * ipv * rsqrt_nr(p + R(kQMin)) < cut) return;
         R eb[3][4][3];
         const R i2p = R(0.5) * ipv;
 #pragma unroll
         for (int d = 0; d < 3; d++) hermite_E<R>(R(bP[d] - sa.A[d]), R(bP[d] - sb.A[d]), i2p, eb[d]);
-        for (int jp = 0; jp < kNPrimPair; jp++) {
+        auto ket = [&](int jp) {
             const double kP[3] = {vk.get(1, jp), vk.get(2, jp), vk.get(3, jp)};
             const R q = R(vk.get(0, jp)), Kk = R(vk.get(4, jp)), iqv = R(vk.get(5, jp));
             const R rs = rsqrt_nr(p + q);                 // 1/sqrt(p + q)
             const R pref = pi25 * ipv * iqv * rs * Kb * Kk;
-            if (fabs(pref) < cut) continue;
+            if (fabs(pref) < cut) return;
             R ek[3][4][3];
             const R i2q = R(0.5) * iqv;
 #pragma unroll
@@ -315,7 +318,22 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
                             acc[((ia * NB + jb) * NC + kc) * ND + ld] += pref * val;
                         }
                 }
+        };
+        // STO-3G: the nine ket primitive pairs unrolled; 6-31G (36, mostly
+        // zero-weight padding for the smaller shells): a plain loop
+        if constexpr (PP <= kNPrimPair) {
+#pragma unroll
+            for (int jp = 0; jp < PP; jp++) ket(jp);
+        } else {
+#pragma unroll 1
+            for (int jp = 0; jp < PP; jp++) ket(jp);
         }
+    };
+    if constexpr (PP <= kNPrimPair) {
+        for (int ip = 0; ip < PP; ip++) bra(ip);
+    } else {
+#pragma unroll 1
+        for (int ip = 0; ip < PP; ip++) bra(ip);
     }
 }
 
@@ -375,7 +393,7 @@ struct EriArgs {
 // kernel on the other stream.)
 constexpr int kEriThreads = 256, kEriQpt = 4;
 
-template <int LA, int LB, int LC, int LD, typename R, typename S>
+template <int LA, int LB, int LC, int LD, typename R, typename S, int PP>
 __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
 {
     constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
@@ -407,8 +425,8 @@ __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
         const Pair P1 = g.pb[ib], P2 = g.pk[ik];
         const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
         R acc[NCOMP];
-        const PairView vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
-        eri_quartet<LA, LB, LC, LD, R, true>(sa, sb, sc, sd, vb, vk, rows, R(g.cut), acc);
+        const PairView<PP> vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
+        eri_quartet<LA, LB, LC, LD, R, true, PP>(sa, sb, sc, sd, vb, vk, rows, R(g.cut), acc);
 #pragma unroll
         for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
     }
@@ -417,25 +435,36 @@ __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
 // Primitive-pair tables of every shell pair of one pair class, stored
 // field-major [f][k][pair] (f = p, Px, Py, Pz, K; k = primitive pair) so that
 // lanes working on consecutive pairs load consecutive addresses.
-__global__ void pair_kernel(const Shell* __restrict__ shells, const Pair* __restrict__ pairs, long npair,
+// pp primitive pairs per shell pair: pp = 9 holds 3 x 3, pp = 36 holds
+// 6 x 6 with the pairs beyond a shell's primitive count padded with zero
+// weight (K = 0, p = 1, P = A), which every integral loop skips.
+__global__ void pair_kernel(const Shell* __restrict__ shells, const Pair* __restrict__ pairs, long npair, int pp,
                             double* __restrict__ out)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npair * kNPrimPair) return;
-    const long ip = t / kNPrimPair;
-    const int k = (int)(t % kNPrimPair), ka = k / kNPrim, kb = k % kNPrim;
+    if (t >= npair * pp) return;
+    const long ip = t / pp;
+    const int per = pp == kNPrimPair ? kNPrim : kPrimMax;
+    const int k = (int)(t % pp), ka = k / per, kb = k % per;
     const Pair pr = pairs[ip];
     const Shell& A = shells[pr.sa];
     const Shell& B = shells[pr.sb];
+    if (ka >= A.np || kb >= B.np) {
+        for (int d = 0; d < 3; d++) out[((size_t)(1 + d) * pp + k) * npair + ip] = A.A[d];
+        out[(size_t)k * npair + ip] = 1.0;
+        out[((size_t)4 * pp + k) * npair + ip] = 0.0;
+        out[((size_t)5 * pp + k) * npair + ip] = 1.0;
+        return;
+    }
     const double a = A.a[ka], b = B.a[kb], p = a + b;
     double r2 = 0.0;
     for (int d = 0; d < 3; d++) {
-        out[((size_t)(1 + d) * kNPrimPair + k) * npair + ip] = (a * A.A[d] + b * B.A[d]) / p;
+        out[((size_t)(1 + d) * pp + k) * npair + ip] = (a * A.A[d] + b * B.A[d]) / p;
         r2 += (A.A[d] - B.A[d]) * (A.A[d] - B.A[d]);
     }
     out[(size_t)k * npair + ip] = p;
-    out[((size_t)4 * kNPrimPair + k) * npair + ip] = A.c[ka] * B.c[kb] * exp(-a * b / p * r2);
-    out[((size_t)5 * kNPrimPair + k) * npair + ip] = 1.0 / p;
+    out[((size_t)4 * pp + k) * npair + ip] = A.c[ka] * B.c[kb] * exp(-a * b / p * r2);
+    out[((size_t)5 * pp + k) * npair + ip] = 1.0 / p;
 }
 
 // ---------------------------------------------------------------------------
@@ -481,8 +510,8 @@ __global__ void int1e_kernel(const MolDesc* __restrict__ mols, const Shell* __re
         lb[d] = lexp(B.L, ib.y, d);
     }
     double s = 0.0, kin = 0.0, v = 0.0;
-    for (int ka = 0; ka < kNPrim; ka++)
-        for (int kb = 0; kb < kNPrim; kb++) {
+    for (int ka = 0; ka < A.np; ka++)
+        for (int kb = 0; kb < B.np; kb++) {
             const double a = A.a[ka], b = B.a[kb], p = a + b, i2p = 0.5 / p;
             double P[3], r2 = 0.0, E[3][2][4][5];
             for (int d = 0; d < 3; d++) {
@@ -558,7 +587,7 @@ __global__ void eri_unpack_kernel(const MolDesc* __restrict__ mols, int m, int c
 // sqrt|(a_i b_j | a_i b_j)|, so |(ab|cd)| <= Q_ab Q_cd for every component.
 // One thread per shell pair of the class; L: angular momenta of the pair.
 // ---------------------------------------------------------------------------
-template <int LA, int LB>
+template <int LA, int LB, int PP>
 __global__ void schwarz_kernel(const Shell* __restrict__ shells, const Pair* __restrict__ pairs,
                                const double* __restrict__ pp, long npair, const double* __restrict__ tab,
                                double* __restrict__ Q)
@@ -568,9 +597,9 @@ __global__ void schwarz_kernel(const Shell* __restrict__ shells, const Pair* __r
     if (i >= npair) return;
     const Pair pr = pairs[i];
     const Shell sa = shells[pr.sa], sb = shells[pr.sb];
-    const PairView v{pp, npair, (int)i};
+    const PairView<PP> v{pp, npair, (int)i};
     double I[NAB * NAB];
-    eri_quartet<LA, LB, LA, LB, double>(sa, sb, sa, sb, v, v, tab, 0.0, I);
+    eri_quartet<LA, LB, LA, LB, double, false, PP>(sa, sb, sa, sb, v, v, tab, 0.0, I);
     double m = 0.0;
 #pragma unroll
     for (int u = 0; u < NAB; u++) m = fmax(m, fabs(I[u * NAB + u]));
@@ -627,7 +656,7 @@ __device__ __forceinline__ double block_max_direct(double mx, double* red)
     return r;
 }
 
-template <int LA, int LB, int LC, int LD, typename A, typename R>
+template <int LA, int LB, int LC, int LD, typename A, typename R, int PP>
 __device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc& md, int chunk, int nchunk, double pmax,
                                              const A* __restrict__ Ps, A* AJ, A* AK)
 {
@@ -649,9 +678,9 @@ __device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc&
         const int ib = md.pair0[cb] + i, ik = md.pair0[ck] + j;
         const Pair P1 = g.pairs[cb][ib], P2 = g.pairs[ck][ik];
         const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
-        const PairView vb{g.pp[cb], g.npp[cb], ib}, vk{g.pp[ck], g.npp[ck], ik};
+        const PairView<PP> vb{g.pp[cb], g.npp[cb], ib}, vk{g.pp[ck], g.npp[ck], ik};
         R I[NCOMP];
-        eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, direct_tab<R>(g), R(g.cut), I);
+        eri_quartet<LA, LB, LC, LD, R, false, PP>(sa, sb, sc, sd, vb, vk, direct_tab<R>(g), R(g.cut), I);
         A Ia[NCOMP];
 #pragma unroll
         for (int k = 0; k < NCOMP; k++) Ia[k] = A(I[k]);
@@ -669,7 +698,7 @@ __device__ __forceinline__ void direct_class(const DirectArgs& g, const MolDesc&
 // shells are staged in LDS (Prow) and their K rows accumulate in LDS (Krow,
 // K_ac, K_ad, K_bc, K_bd), J_ab in registers; both are added to the partials
 // once per bra, so only J_cd reaches global memory per quartet.
-template <int LA, int LB, int LC, int LD, typename R>
+template <int LA, int LB, int LC, int LD, typename R, int PP>
 __device__ __forceinline__ void direct_class_rows(const DirectArgs& g, const MolDesc& md, int chunk, int nchunk,
                                                   double pmax, const double* __restrict__ Pg, double* AJ, double* AK,
                                                   double* Prow, double* Krow, const double* boys_rows_l)
@@ -724,18 +753,18 @@ __device__ __forceinline__ void direct_class_rows(const DirectArgs& g, const Mol
             }
         const Pair P1 = g.pairs[cb][ib];
         const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb];
-        const PairView vb{g.pp[cb], g.npp[cb], ib};
+        const PairView<PP> vb{g.pp[cb], g.npp[cb], ib};
         for (int t = threadIdx.x; t < seg; t += blockDim.x) {
             const int j = j0 + t;
             const int ik = md.pair0[ck] + j;
             const Pair P2 = g.pairs[ck][ik];
             const Shell sc = g.shells[P2.sa], sd = g.shells[P2.sb];
-            const PairView vk{g.pp[ck], g.npp[ck], ik};
+            const PairView<PP> vk{g.pp[ck], g.npp[ck], ik};
             R Ir[NCOMP];
             if constexpr (std::is_same<R, double>::value)
-                eri_quartet<LA, LB, LC, LD, R, true>(sa, sb, sc, sd, vb, vk, boys_rows_l, R(g.cut), Ir);
+                eri_quartet<LA, LB, LC, LD, R, true, PP>(sa, sb, sc, sd, vb, vk, boys_rows_l, R(g.cut), Ir);
             else
-                eri_quartet<LA, LB, LC, LD, R>(sa, sb, sc, sd, vb, vk, direct_tab<R>(g), R(g.cut), Ir);
+                eri_quartet<LA, LB, LC, LD, R, false, PP>(sa, sb, sc, sd, vb, vk, direct_tab<R>(g), R(g.cut), Ir);
             double I[NCOMP];
 #pragma unroll
             for (int k = 0; k < NCOMP; k++) I[k] = double(Ir[k]);
@@ -768,7 +797,7 @@ __device__ __forceinline__ void direct_class_rows(const DirectArgs& g, const Mol
 
 // Molecules whose J/K accumulators fit in LDS: ΔP, J and K in LDS, all six
 // classes in one work group per item, the accumulators written out once.
-template <typename A, typename R>
+template <typename A, typename R, int PP>
 __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
 {
     const JkItem it = g.items[blockIdx.x];
@@ -791,12 +820,12 @@ __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
         AK[i] = A(0);
     }
     const double pmax = block_max_direct(mx, red);
-    direct_class<0, 0, 0, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
-    direct_class<1, 0, 0, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
-    direct_class<1, 0, 1, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
-    direct_class<1, 1, 0, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
-    direct_class<1, 1, 1, 0, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
-    direct_class<1, 1, 1, 1, A, R>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<0, 0, 0, 0, A, R, PP>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 0, 0, 0, A, R, PP>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 0, 1, 0, A, R, PP>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 1, 0, 0, A, R, PP>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 1, 1, 0, A, R, PP>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
+    direct_class<1, 1, 1, 1, A, R, PP>(g, md, it.chunk, it.nchunk, pmax, Pl, AJ, AK);
     __syncthreads();
     A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
@@ -808,7 +837,7 @@ __global__ __launch_bounds__(kDirectThreads) void direct_jk_kernel(DirectArgs g)
 // Larger molecules: one launch per class (each class gets its own register
 // allocation), ΔP materialised in global memory (dP), J/K partials per item
 // in global memory, zeroed by the first launch.
-template <int LA, int LB, int LC, int LD, typename R>
+template <int LA, int LB, int LC, int LD, typename R, int PP>
 __global__ __launch_bounds__(kDirectThreads) void direct_rows_kernel(DirectArgs g, int zero)
 {
     const JkItem it = g.items[blockIdx.x];
@@ -838,12 +867,12 @@ __global__ __launch_bounds__(kDirectThreads) void direct_rows_kernel(DirectArgs 
         for (int t = threadIdx.x; t < kBoysNTR * kBoysKR / 2; t += blockDim.x) ((double2*)rows)[t] = src[t];
         __syncthreads();
     }
-    direct_class_rows<LA, LB, LC, LD, R>(g, md, it.chunk, it.nchunk, pmax, dP, AJ, AK, Prow, Krow, rows);
+    direct_class_rows<LA, LB, LC, LD, R, PP>(g, md, it.chunk, it.nchunk, pmax, dP, AJ, AK, Prow, Krow, rows);
 }
 
 // out[k] = in[perm[k]] for the per-pair arrays of one pair class (pairs,
 // AO offsets, Schwarz factors and the field-major primitive-pair table).
-__global__ void permute_pairs_kernel(const int* __restrict__ perm, long n, const Pair* __restrict__ pairs_in,
+__global__ void permute_pairs_kernel(const int* __restrict__ perm, long n, int pp, const Pair* __restrict__ pairs_in,
                                      const int2* __restrict__ pao_in, const double* __restrict__ pp_in,
                                      const double* __restrict__ Q_in, Pair* __restrict__ pairs_out,
                                      int2* __restrict__ pao_out, double* __restrict__ pp_out, double* __restrict__ Q_out)
@@ -854,7 +883,7 @@ __global__ void permute_pairs_kernel(const int* __restrict__ perm, long n, const
     pairs_out[k] = pairs_in[src];
     pao_out[k] = pao_in[src];
     Q_out[k] = Q_in[src];
-    for (int f = 0; f < kPairFields * kNPrimPair; f++) pp_out[(size_t)f * n + k] = pp_in[(size_t)f * n + src];
+    for (int f = 0; f < kPairFields * pp; f++) pp_out[(size_t)f * n + k] = pp_in[(size_t)f * n + src];
 }
 
 ks_status launch_permute_pairs(ks_batch* b, int c, const int* perm, Pair* pairs_out, int2* pao_out, double* pp_out,
@@ -863,7 +892,7 @@ ks_status launch_permute_pairs(ks_batch* b, int c, const int* perm, Pair* pairs_
     const long n = b->npairs[c];
     if (!n) return KS_OK;
     hipLaunchKernelGGL(permute_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, perm, n,
-                       b->d_pairs[c], b->d_pair_ao[c], b->d_pp[c], b->d_Q[c], pairs_out, pao_out, pp_out, Q_out);
+                       b->pp, b->d_pairs[c], b->d_pair_ao[c], b->d_pp[c], b->d_Q[c], pairs_out, pao_out, pp_out, Q_out);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
@@ -886,16 +915,16 @@ ks_status launch_int1e(ks_batch* b)
 ks_status launch_pairs(ks_batch* b)
 {
     for (int c = 0; c < 3; c++) {
-        long n = b->npairs[c] * kNPrimPair;
+        long n = b->npairs[c] * b->pp;
         if (!n) continue;
         hipLaunchKernelGGL(pair_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, b->d_shells,
-                           b->d_pairs[c], b->npairs[c], b->d_pp[c]);
+                           b->d_pairs[c], b->npairs[c], b->pp, b->d_pp[c]);
         KS_HIP(hipGetLastError());
     }
     return KS_OK;
 }
 
-template <int LA, int LB, int LC, int LD, typename R, typename S>
+template <int LA, int LB, int LC, int LD, typename R, typename S, int PP>
 static ks_status launch_class(ks_batch* b, int c)
 {
     if (!b->nq[c]) return KS_OK;
@@ -920,22 +949,22 @@ static ks_status launch_class(ks_batch* b, int c)
     g.rows = b->d_boys_rows;
     const long per = (long)kEriThreads * kEriQpt;
     const long nb = (g.nq + per - 1) / per;
-    hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S>), dim3((unsigned)nb), dim3(kEriThreads), 0, b->stream,
-                       g);
+    hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S, PP>), dim3((unsigned)nb), dim3(kEriThreads), 0,
+                       b->stream, g);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
 
-template <typename R, typename S>
+template <typename R, typename S, int PP>
 static ks_status launch_all_classes(ks_batch* b)
 {
     ks_status st;
-    if ((st = launch_class<0, 0, 0, 0, R, S>(b, 0))) return st;
-    if ((st = launch_class<1, 0, 0, 0, R, S>(b, 1))) return st;
-    if ((st = launch_class<1, 0, 1, 0, R, S>(b, 2))) return st;
-    if ((st = launch_class<1, 1, 0, 0, R, S>(b, 3))) return st;
-    if ((st = launch_class<1, 1, 1, 0, R, S>(b, 4))) return st;
-    if ((st = launch_class<1, 1, 1, 1, R, S>(b, 5))) return st;
+    if ((st = launch_class<0, 0, 0, 0, R, S, PP>(b, 0))) return st;
+    if ((st = launch_class<1, 0, 0, 0, R, S, PP>(b, 1))) return st;
+    if ((st = launch_class<1, 0, 1, 0, R, S, PP>(b, 2))) return st;
+    if ((st = launch_class<1, 1, 0, 0, R, S, PP>(b, 3))) return st;
+    if ((st = launch_class<1, 1, 1, 0, R, S, PP>(b, 4))) return st;
+    if ((st = launch_class<1, 1, 1, 1, R, S, PP>(b, 5))) return st;
     return KS_OK;
 }
 
@@ -944,8 +973,11 @@ ks_status launch_eri(ks_batch* b)
     KTimer tm(b, "eri");
     // FP64 evaluation in both paths: evaluated in FP32, a 130-function
     // molecule's SCF energy moved by 1.2e-4 Ha against the oracle
-    if (b->opt.prec == KS_MIXED) return launch_all_classes<double, float>(b);
-    return launch_all_classes<double, double>(b);
+    if (b->pp == kPrimPairMax)
+        return b->opt.prec == KS_MIXED ? launch_all_classes<double, float, kPrimPairMax>(b)
+                                       : launch_all_classes<double, double, kPrimPairMax>(b);
+    if (b->opt.prec == KS_MIXED) return launch_all_classes<double, float, kNPrimPair>(b);
+    return launch_all_classes<double, double, kNPrimPair>(b);
 }
 
 ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out)
@@ -967,12 +999,12 @@ ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out)
     return KS_OK;
 }
 
-template <int LA, int LB>
+template <int LA, int LB, int PP>
 static ks_status launch_schwarz_class(ks_batch* b, int c)
 {
     const long n = b->npairs[c];
     if (!n) return KS_OK;
-    hipLaunchKernelGGL((schwarz_kernel<LA, LB>), dim3((unsigned)((n + 127) / 128)), dim3(128), 0, b->stream,
+    hipLaunchKernelGGL((schwarz_kernel<LA, LB, PP>), dim3((unsigned)((n + 127) / 128)), dim3(128), 0, b->stream,
                        b->d_shells, b->d_pairs[c], b->d_pp[c], n, b->d_boys, b->d_Q[c]);
     KS_HIP(hipGetLastError());
     return KS_OK;
@@ -982,26 +1014,32 @@ ks_status launch_schwarz(ks_batch* b)
 {
     KTimer tm(b, "schwarz");
     ks_status st;
-    if ((st = launch_schwarz_class<0, 0>(b, 0))) return st;
-    if ((st = launch_schwarz_class<1, 0>(b, 1))) return st;
-    if ((st = launch_schwarz_class<1, 1>(b, 2))) return st;
+    if (b->pp == kPrimPairMax) {
+        if ((st = launch_schwarz_class<0, 0, kPrimPairMax>(b, 0))) return st;
+        if ((st = launch_schwarz_class<1, 0, kPrimPairMax>(b, 1))) return st;
+        if ((st = launch_schwarz_class<1, 1, kPrimPairMax>(b, 2))) return st;
+    } else {
+        if ((st = launch_schwarz_class<0, 0, kNPrimPair>(b, 0))) return st;
+        if ((st = launch_schwarz_class<1, 0, kNPrimPair>(b, 1))) return st;
+        if ((st = launch_schwarz_class<1, 1, kNPrimPair>(b, 2))) return st;
+    }
     b->schwarz_done = true;
     return KS_OK;
 }
 
-template <int LA, int LB, int LC, int LD, typename R>
+template <int LA, int LB, int LC, int LD, typename R, int PP>
 static ks_status launch_direct_rows(ks_batch* b, const DirectArgs& g, size_t lds, int zero)
 {
-    KS_HIP(hipFuncSetAttribute((const void*)direct_rows_kernel<LA, LB, LC, LD, R>,
+    KS_HIP(hipFuncSetAttribute((const void*)direct_rows_kernel<LA, LB, LC, LD, R, PP>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((direct_rows_kernel<LA, LB, LC, LD, R>), dim3((unsigned)b->jk_items.size()),
+    hipLaunchKernelGGL((direct_rows_kernel<LA, LB, LC, LD, R, PP>), dim3((unsigned)b->jk_items.size()),
                        dim3(kDirectThreads), lds, b->stream, g, zero);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
 
 // Integrals evaluated in R (the Boys table of that type), accumulated in A.
-template <typename A, typename R, bool GLOBAL>
+template <typename A, typename R, bool GLOBAL, int PP>
 static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, bool incremental)
 {
     DirectArgs g;
@@ -1038,17 +1076,17 @@ static ks_status run_direct_jk(ks_batch* b, const double* P, bool only_active, b
         static_assert(std::is_same<A, double>::value, "global partials are FP64");
         const size_t lds = (kBoysNTR * kBoysKR + 12 * (size_t)maxn) * sizeof(double);
         ks_status st;
-        if ((st = launch_direct_rows<0, 0, 0, 0, R>(b, g, lds, 1))) return st;
-        if ((st = launch_direct_rows<1, 0, 0, 0, R>(b, g, lds, 0))) return st;
-        if ((st = launch_direct_rows<1, 0, 1, 0, R>(b, g, lds, 0))) return st;
-        if ((st = launch_direct_rows<1, 1, 0, 0, R>(b, g, lds, 0))) return st;
-        if ((st = launch_direct_rows<1, 1, 1, 0, R>(b, g, lds, 0))) return st;
-        return launch_direct_rows<1, 1, 1, 1, R>(b, g, lds, 0);
+        if ((st = launch_direct_rows<0, 0, 0, 0, R, PP>(b, g, lds, 1))) return st;
+        if ((st = launch_direct_rows<1, 0, 0, 0, R, PP>(b, g, lds, 0))) return st;
+        if ((st = launch_direct_rows<1, 0, 1, 0, R, PP>(b, g, lds, 0))) return st;
+        if ((st = launch_direct_rows<1, 1, 0, 0, R, PP>(b, g, lds, 0))) return st;
+        if ((st = launch_direct_rows<1, 1, 1, 0, R, PP>(b, g, lds, 0))) return st;
+        return launch_direct_rows<1, 1, 1, 1, R, PP>(b, g, lds, 0);
     } else {
         const size_t lds = 3 * (size_t)maxn * maxn * sizeof(A);
-        KS_HIP(hipFuncSetAttribute((const void*)direct_jk_kernel<A, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-        hipLaunchKernelGGL((direct_jk_kernel<A, R>), dim3((unsigned)b->jk_items.size()), dim3(kDirectThreads), lds,
+        KS_HIP(hipFuncSetAttribute((const void*)direct_jk_kernel<A, R, PP>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((direct_jk_kernel<A, R, PP>), dim3((unsigned)b->jk_items.size()), dim3(kDirectThreads), lds,
                            b->stream, g);
         KS_HIP(hipGetLastError());
         return KS_OK;
@@ -1069,9 +1107,15 @@ ks_status launch_direct_jk(ks_batch* b, const double* P, double* J, double* K, b
     const int mode = jk_mode(b);
     const bool f64 = mode != 1;
     // integrals evaluated in FP64 in both paths (as in the stored build)
-    ks_status st = mode == 0 ? run_direct_jk<double, double, false>(b, P, only_active, incremental)
-                 : mode == 1 ? run_direct_jk<float, double, false>(b, P, only_active, incremental)
-                             : run_direct_jk<double, double, true>(b, P, only_active, incremental);
+    ks_status st;
+    if (b->pp == kPrimPairMax)
+        st = mode == 0 ? run_direct_jk<double, double, false, kPrimPairMax>(b, P, only_active, incremental)
+           : mode == 1 ? run_direct_jk<float, double, false, kPrimPairMax>(b, P, only_active, incremental)
+                       : run_direct_jk<double, double, true, kPrimPairMax>(b, P, only_active, incremental);
+    else
+        st = mode == 0 ? run_direct_jk<double, double, false, kNPrimPair>(b, P, only_active, incremental)
+           : mode == 1 ? run_direct_jk<float, double, false, kNPrimPair>(b, P, only_active, incremental)
+                       : run_direct_jk<double, double, true, kNPrimPair>(b, P, only_active, incremental);
     if (st) return st;
     return launch_jk_reduce(b, f64, P, J, K, only_active, incremental, track);
 }

@@ -375,8 +375,10 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
     }
 }
 
-// Diagonal atomic-occupation density: H 1s 1; C/N/O/F 1s 2, 2s 2, 2p (Z-4)/3
-// per component, scaled so that tr(P S) = tr(P) = N_e.
+// Diagonal atomic-occupation density from the shells' neutral-atom
+// occupations (STO-3G: H 1s 1; C/N/O/F 1s 2, 2s 2, 2p (Z-4)/3 per component;
+// 6-31G: the valence split evenly over the inner and outer shells), scaled
+// so that tr(P S) = tr(P) = N_e.
 __global__ __launch_bounds__(kScfThreads) void atom_guess_kernel(const MolDesc* __restrict__ mols,
                                                                  const Shell* __restrict__ shells,
                                                                  const double* __restrict__ Zat, double* __restrict__ P)
@@ -391,8 +393,7 @@ __global__ __launch_bounds__(kScfThreads) void atom_guess_kernel(const MolDesc* 
     double s = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < md.nshell; i += blockDim.x) {
         const Shell& sh = shells[md.shell0 + i];
-        const double Z = Zat[md.atom0 + sh.atom];
-        const double occ = Z == 1.0 ? 1.0 : (sh.L == 1 ? (Z - 4.0) / 3.0 : 2.0);
+        const double occ = sh.occ;      // neutral-atom occupation per function (set with the basis)
         for (int k = 0; k < (sh.L ? 3 : 1); k++) {
             Pm[(sh.ao + k) * N + sh.ao + k] = occ;
             two_sum_add(s, c, occ);

@@ -292,6 +292,7 @@ struct XcArgs {
     int vwn5;
     int only_active;
     int ns_max;             // largest shell count of the batch (LDS shell table)
+    int npm;                // primitives per shell in the shell table (3 STO-3G, 6 6-31G; zero-padded)
 };
 
 // Shell table of one molecule as the XC kernel keeps it in LDS: centres,
@@ -299,7 +300,7 @@ struct XcArgs {
 template <typename T>
 struct ShellLds {
     double* A;      // [ns][3]
-    T* ac;          // [ns][6]: a0 a1 a2 c0 c1 c2
+    T* ac;          // [ns][2 npm]: exponents, then coefficients (zero past the shell's count)
     int* info;      // [ns]: ao | L << 16
 };
 
@@ -314,10 +315,10 @@ __host__ __device__ constexpr size_t al32(size_t x) { return (x + 31) & ~(size_t
 __host__ __device__ constexpr int xc_ldp(int np) { return np + 4; }
 __host__ __device__ constexpr int xc_ldg(int bp) { return bp + 4; }
 __host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np, int ns,
-                                                      bool pglobal = false)
+                                                      bool pglobal = false, int npm = kNPrim)
 {
     return al32((size_t)bp * 4 * sizeof(double)) + al32((size_t)nw * sizeof(double))
-           + al32((size_t)ns * 3 * sizeof(double)) + al32((size_t)ns * 6 * es) + al32((size_t)bp * 4 * es)
+           + al32((size_t)ns * 3 * sizeof(double)) + al32((size_t)ns * 2 * npm * es) + al32((size_t)bp * 4 * es)
            + al32((size_t)bp * 9 * es) + al32((size_t)(np / 16) * 4 * bp * es)
            + (pglobal ? 0 : al32((size_t)np * xc_ldp(np) * es))
            + al32((size_t)(es == sizeof(float) ? 5 : 4) * np * xc_ldg(bp) * es) + al32((size_t)ns * sizeof(int));
@@ -568,7 +569,8 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     double* wsum = (double*)take(NW * sizeof(double));        // [NW]
     ShellLds<T> shl;
     shl.A = (double*)take((size_t)g.ns_max * 3 * sizeof(double));
-    shl.ac = (T*)take((size_t)g.ns_max * 6 * sizeof(T));
+    const int npm = g.npm;
+    shl.ac = (T*)take((size_t)g.ns_max * 2 * npm * sizeof(T));
     T* coef = (T*)take(BP * 4 * sizeof(T));                   // [BP][4]: rho, grad rho
     T* fpart = (T*)take(BP * 9 * sizeof(T));                  // [3][BP][3]: e, v_rho, v_sigma per part
     T* rpart = (T*)take((size_t)NT * 4 * BP * sizeof(T));     // [NT][4][BP]
@@ -587,10 +589,10 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     for (int i = tid; i < md.nshell; i += NTH) {
         const Shell& S = sh[i];
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            shl.A[3 * i + k] = S.A[k];
-            shl.ac[6 * i + k] = (T)S.a[k];
-            shl.ac[6 * i + 3 + k] = (T)S.c[k];
+        for (int k = 0; k < 3; k++) shl.A[3 * i + k] = S.A[k];
+        for (int k = 0; k < npm; k++) {
+            shl.ac[2 * npm * i + k] = (T)S.a[k];
+            shl.ac[2 * npm * i + npm + k] = (T)S.c[k];
         }
         shl.info[i] = S.ao | (S.L << 16);
     }
@@ -636,22 +638,24 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             for (int s = grp; s < md.nshell; s += NG) {
                 const T dx = (T)(px - shl.A[3 * s]), dy = (T)(py - shl.A[3 * s + 1]), dz = (T)(pz - shl.A[3 * s + 2]);
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const T* ac = shl.ac + 6 * s;
+                const T* ac = shl.ac + 2 * npm * s;
                 T R = T(0), dR = T(0);
-#pragma unroll
-                for (int k = 0; k < kNPrim; k++) {
+                auto prim = [&](int k) {
                     const T ar = ac[k] * r2;
                     if constexpr (sizeof(T) == 4) {
                         // the hardware exp2 flushes to 0 far below the FP32 range
-                        const T e = ac[3 + k] * fast_exp(-ar);
+                        const T e = ac[npm + k] * fast_exp(-ar);
                         R += e;
                         dR -= T(2) * ac[k] * e;
                     } else if (ar < T(80)) {
-                        const T e = ac[3 + k] * fast_exp(-ar);
+                        const T e = ac[npm + k] * fast_exp(-ar);
                         R += e;
                         dR -= T(2) * ac[k] * e;
                     }
-                }
+                };
+#pragma unroll
+                for (int k = 0; k < kNPrim; k++) prim(k);
+                for (int k = kNPrim; k < npm; k++) prim(k);     // 6-31G core shells
                 const int info = shl.info[s], mu = info & 0xffff;
                 T* o = Phi + mu * LDG + gp;
                 auto put_phi = [&](int off, T v) {
@@ -849,6 +853,7 @@ XcShape xc_shape(const ks_batch* b)
     XcShape s;
     const bool f32 = b->opt.prec == KS_MIXED;
     const size_t es = f32 ? sizeof(float) : sizeof(double);
+    const int npm = b->pp == kPrimPairMax ? kPrimMax : kNPrim;
     s.bp = f32 ? 64 : 32;
     s.nw = 8;
     if (b->opt.xc_points > 0 || b->opt.xc_waves > 0) {
@@ -862,11 +867,11 @@ XcShape xc_shape(const ks_batch* b)
         s.bp = 16;
         s.nw = 8;
         s.pglobal = true;
-        s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, true);
+        s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, true, npm);
         return s;
     }
-    while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell) > kLdsMax) s.bp /= 2;
-    s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell);
+    while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, false, npm) > kLdsMax) s.bp /= 2;
+    s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, false, npm);
     return s;
 }
 
@@ -907,6 +912,7 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
     g.part_exc = b->d_xc_exc;
     g.part_stride = (long)b->max_np * b->max_np;
     g.ns_max = b->max_nshell;
+    g.npm = b->pp == kPrimPairMax ? kPrimMax : kNPrim;
     g.vwn5 = b->opt.xc == KS_XC_B3LYP5;
     g.only_active = only_active;
     const XcShape s = xc_shape(b);

@@ -20,6 +20,8 @@ namespace ks {
 constexpr int kMaxNbf = 224;
 constexpr int kNPrim = 3;       // STO-3G: three primitives per shell
 constexpr int kNPrimPair = kNPrim * kNPrim;
+constexpr int kPrimMax = 6;     // 6-31G: up to six (the core s shell)
+constexpr int kPrimPairMax = kPrimMax * kPrimMax;
 constexpr int kMaxDiis = 8;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kBohrAng = 0.52917721092;
@@ -56,12 +58,13 @@ constexpr int kBoysLR = 5;
 // x contracted renormalisation.
 struct Shell {
     double A[3];
-    double a[kNPrim];
-    double c[kNPrim];
+    double a[kPrimMax];
+    double c[kPrimMax];
+    double occ; // initial-guess occupation per function of the shell
     int L;      // 0 = s, 1 = p
     int ao;     // first AO index inside its molecule
     int atom;   // atom index inside its molecule
-    int pad;
+    int np;     // primitives (3 in STO-3G; 6, 3 or 1 in 6-31G)
 };
 
 // Primitive-pair data of a shell pair (McMurchie-Davidson Gaussian product):
@@ -142,6 +145,7 @@ struct ks_batch {
     int max_np = 0;
     int max_nshell = 0;
     double a0 = 0.2;
+    int pp = ks::kNPrimPair;        // primitive pairs per shell pair in the pair tables (9 STO-3G, 36 6-31G)
     std::vector<ks::MolDesc> mol;
     std::vector<ks::Shell> shells;
     std::vector<int> Z;

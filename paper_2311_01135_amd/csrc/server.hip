@@ -84,11 +84,12 @@ static size_t estimate_bytes(const ks_options& o, int natom, int nbf)
     return (size_t)(eri + grid + mats + parts) + (1u << 20);
 }
 
-static int validate(const int* Z, const double* xyz, int n, int charge, int* nbf)
+static int validate(const int* Z, const double* xyz, int n, int charge, int basis, int* nbf)
 {
     int ne = -charge, nb = 0;
     for (int a = 0; a < n; a++) {
         if (Z[a] != 1 && Z[a] != 6 && Z[a] != 7 && Z[a] != 8 && Z[a] != 9) return 0;
+        if (basis == KS_BASIS_631G && Z[a] == 9) return 0;
         for (int k = 0; k < 3; k++)
             if (!std::isfinite(xyz[3 * a + k])) return 0;
         for (int c = 0; c < a; c++) {
@@ -97,7 +98,7 @@ static int validate(const int* Z, const double* xyz, int n, int charge, int* nbf
             if (std::sqrt(d2) / kBohrAng < 0.1) return 0;
         }
         ne += Z[a];
-        nb += Z[a] == 1 ? 1 : 5;
+        nb += basis == KS_BASIS_631G ? (Z[a] == 1 ? 2 : 9) : (Z[a] == 1 ? 1 : 5);
     }
     *nbf = nb;
     return n > 0 && ne > 0 && !(ne & 1);
@@ -227,7 +228,7 @@ ks_status ks_server_submit(ks_server* s, int n_atoms, const int* Z, const double
         return KS_EINVAL;
     }
     int nbf = 0;
-    if (!validate(Z, xyz_angstrom, n_atoms, charge, &nbf)) {
+    if (!validate(Z, xyz_angstrom, n_atoms, charge, s->opt.basis, &nbf)) {
         set_error("invalid molecule (element, coordinates, spacing or odd electron count)");
         return KS_EINVAL;
     }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libks.so")
 KS_XC_HF, KS_XC_B3LYP, KS_XC_B3LYP5 = 0, 1, 2
 KS_FP64, KS_MIXED = 0, 1
 KS_GUESS_ATOM, KS_GUESS_CORE = 0, 1
+KS_BASIS_STO3G, KS_BASIS_631G = 0, 1
 MOL_ACTIVE, MOL_CONVERGED, MOL_MAXITER, MOL_DIVERGED = 0, 1, 2, 3
 MATRIX = {"S": 0, "T": 1, "V": 2, "X": 3, "F": 4, "P": 5, "J": 6, "K": 7, "Vxc": 8}
 STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", -4: "KS_ENOCONV",
@@ -45,7 +46,7 @@ class Options(C.Structure):
                 ("max_iter", C.c_int), ("diis_space", C.c_int), ("jk_chunks", C.c_int),
                 ("xc_chunks", C.c_int), ("guess", C.c_int), ("xc_points", C.c_int),
                 ("xc_waves", C.c_int), ("direct", C.c_int), ("schwarz_tol", C.c_double),
-                ("graphs", C.c_int)]
+                ("basis", C.c_int), ("graphs", C.c_int)]
 
 
 _lib = None

@@ -378,6 +378,23 @@ def nbf_sto3g(Z) -> int:
     return int((Z == 1).sum() + 5 * (Z > 1).sum())
 
 
+def nbf_631g(Z) -> int:
+    """Number of 6-31G functions: 2 per H, 9 per C/N/O (a count, not arithmetic)."""
+    Z = np.asarray(Z)
+    return int(2 * (Z == 1).sum() + 9 * (Z > 1).sum())
+
+
+def tree_without(n_heavy: int, seed: int, index: int, exclude=(9,)):
+    """First molecule tree(n_heavy, seed, index + k), k = 0, 1, ..., with no
+    element in exclude (6-31G here covers H, C, N, O).  Returns (Z, xyz, k)."""
+    k = 0
+    while True:
+        z, x = tree(n_heavy, seed, index + k)
+        if not np.isin(z, exclude).any():
+            return z, x, k
+        k += 1
+
+
 def pack(mols):
     """Concatenate a list of (Z, xyz) into the flat arrays the C ABI takes."""
     n_atoms = np.array([len(z) for z, _ in mols], dtype=np.int32)
