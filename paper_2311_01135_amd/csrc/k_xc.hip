@@ -300,7 +300,7 @@ struct XcArgs {
 template <typename T>
 struct ShellLds {
     double* A;      // [ns][3]
-    T* ac;          // [ns][2 npm]: exponents, then coefficients (zero past the shell's count)
+    T* ac;          // [ns][12]: a0 a1 a2 c0 c1 c2, then a3 a4 a5 c3 c4 c5 (zero past the shell's count)
     int* info;      // [ns]: ao | L << 16
 };
 
@@ -315,10 +315,10 @@ __host__ __device__ constexpr size_t al32(size_t x) { return (x + 31) & ~(size_t
 __host__ __device__ constexpr int xc_ldp(int np) { return np + 4; }
 __host__ __device__ constexpr int xc_ldg(int bp) { return bp + 4; }
 __host__ __device__ constexpr size_t xc_lds_bytes_for(size_t es, int bp, int nw, int np, int ns,
-                                                      bool pglobal = false, int npm = kNPrim)
+                                                      bool pglobal = false)
 {
     return al32((size_t)bp * 4 * sizeof(double)) + al32((size_t)nw * sizeof(double))
-           + al32((size_t)ns * 3 * sizeof(double)) + al32((size_t)ns * 2 * npm * es) + al32((size_t)bp * 4 * es)
+           + al32((size_t)ns * 3 * sizeof(double)) + al32((size_t)ns * 2 * kPrimMax * es) + al32((size_t)bp * 4 * es)
            + al32((size_t)bp * 9 * es) + al32((size_t)(np / 16) * 4 * bp * es)
            + (pglobal ? 0 : al32((size_t)np * xc_ldp(np) * es))
            + al32((size_t)(es == sizeof(float) ? 5 : 4) * np * xc_ldg(bp) * es) + al32((size_t)ns * sizeof(int));
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     ShellLds<T> shl;
     shl.A = (double*)take((size_t)g.ns_max * 3 * sizeof(double));
     const int npm = g.npm;
-    shl.ac = (T*)take((size_t)g.ns_max * 2 * npm * sizeof(T));
+    shl.ac = (T*)take((size_t)g.ns_max * 2 * kPrimMax * sizeof(T));
     T* coef = (T*)take(BP * 4 * sizeof(T));                   // [BP][4]: rho, grad rho
     T* fpart = (T*)take(BP * 9 * sizeof(T));                  // [3][BP][3]: e, v_rho, v_sigma per part
     T* rpart = (T*)take((size_t)NT * 4 * BP * sizeof(T));     // [NT][4][BP]
@@ -590,9 +590,10 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
         const Shell& S = sh[i];
 #pragma unroll
         for (int k = 0; k < 3; k++) shl.A[3 * i + k] = S.A[k];
-        for (int k = 0; k < npm; k++) {
-            shl.ac[2 * npm * i + k] = (T)S.a[k];
-            shl.ac[2 * npm * i + npm + k] = (T)S.c[k];
+        for (int k = 0; k < kPrimMax; k++) {
+            const int h = k / kNPrim, j = k % kNPrim;
+            shl.ac[2 * kPrimMax * i + 2 * kNPrim * h + j] = (T)S.a[k];
+            shl.ac[2 * kPrimMax * i + 2 * kNPrim * h + kNPrim + j] = (T)S.c[k];
         }
         shl.info[i] = S.ao | (S.L << 16);
     }
@@ -638,24 +639,27 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             for (int s = grp; s < md.nshell; s += NG) {
                 const T dx = (T)(px - shl.A[3 * s]), dy = (T)(py - shl.A[3 * s + 1]), dz = (T)(pz - shl.A[3 * s + 2]);
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const T* ac = shl.ac + 2 * npm * s;
+                const T* ac = shl.ac + 2 * kPrimMax * s;
                 T R = T(0), dR = T(0);
-                auto prim = [&](int k) {
-                    const T ar = ac[k] * r2;
+                auto prim = [&](const T* q, int k) {   // q: a block of three exponents, three coefficients
+                    const T ar = q[k] * r2;
                     if constexpr (sizeof(T) == 4) {
                         // the hardware exp2 flushes to 0 far below the FP32 range
-                        const T e = ac[npm + k] * fast_exp(-ar);
+                        const T e = q[kNPrim + k] * fast_exp(-ar);
                         R += e;
-                        dR -= T(2) * ac[k] * e;
+                        dR -= T(2) * q[k] * e;
                     } else if (ar < T(80)) {
-                        const T e = ac[npm + k] * fast_exp(-ar);
+                        const T e = q[kNPrim + k] * fast_exp(-ar);
                         R += e;
-                        dR -= T(2) * ac[k] * e;
+                        dR -= T(2) * q[k] * e;
                     }
                 };
 #pragma unroll
-                for (int k = 0; k < kNPrim; k++) prim(k);
-                for (int k = kNPrim; k < npm; k++) prim(k);     // 6-31G core shells
+                for (int k = 0; k < kNPrim; k++) prim(ac, k);
+                if (npm > kNPrim) {                              // 6-31G core shells
+#pragma unroll
+                    for (int k = 0; k < kNPrim; k++) prim(ac + 2 * kNPrim, k);
+                }
                 const int info = shl.info[s], mu = info & 0xffff;
                 T* o = Phi + mu * LDG + gp;
                 auto put_phi = [&](int off, T v) {
@@ -853,7 +857,6 @@ XcShape xc_shape(const ks_batch* b)
     XcShape s;
     const bool f32 = b->opt.prec == KS_MIXED;
     const size_t es = f32 ? sizeof(float) : sizeof(double);
-    const int npm = b->pp == kPrimPairMax ? kPrimMax : kNPrim;
     s.bp = f32 ? 64 : 32;
     s.nw = 8;
     if (b->opt.xc_points > 0 || b->opt.xc_waves > 0) {
@@ -867,11 +870,11 @@ XcShape xc_shape(const ks_batch* b)
         s.bp = 16;
         s.nw = 8;
         s.pglobal = true;
-        s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, true, npm);
+        s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, true);
         return s;
     }
-    while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, false, npm) > kLdsMax) s.bp /= 2;
-    s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell, false, npm);
+    while (s.bp > 16 && xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell) > kLdsMax) s.bp /= 2;
+    s.lds = xc_lds_bytes_for(es, s.bp, s.nw, b->max_np, b->max_nshell);
     return s;
 }
 
