@@ -56,6 +56,8 @@ def parse():
     p.add_argument("--grid", type=str, default="50,12,24", help="radial,theta,phi points per atom")
     p.add_argument("--direct", action="store_true", help="integral-direct J/K (ERIs recomputed every iteration)")
     p.add_argument("--schwarz-tol", type=float, default=0.0, help="Schwarz screening threshold (0 = off)")
+    p.add_argument("--basis", choices=["sto-3g", "6-31g"], default="sto-3g",
+                   help="6-31G covers H, C, N, O: molecules with F are replaced by F-free trees of the same size")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="run one plain streaming copy of this many MiB before the timed region (the reference "
                         "kernel that scales hardware byte counters)")
@@ -88,6 +90,9 @@ def measured_traffic(args, prec_name):
     if (t.get("source_sha256") != sha or w.get("n_mol") != args.n_mol or w.get("seed") != args.seed
             or w.get("heavy") != args.heavy or w.get("precision") != prec_name):
         return None
+    # the counters were taken on the default STO-3G, stored-integral, 50x12x24 workload
+    if args.basis != "sto-3g" or args.direct or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24):
+        return None
     return t["traffic_bytes_per_launch"]
 
 
@@ -113,7 +118,8 @@ def oracle_subset(args, res, res64):
     that calls only the oracle), when the stored set is this workload's."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
                         "oracle_scf_seed2_first64.json")
-    if not os.path.exists(path) or args.direct or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24):
+    if (not os.path.exists(path) or args.direct or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24)
+            or args.basis != "sto-3g"):
         return None
     with open(path) as f:
         doc = json.load(f)
@@ -136,7 +142,10 @@ def oracle_subset(args, res, res64):
 def solve_batch(ks, mols, prec, timing, args):
     from paper_2311_01135_amd import autotune, molgen
     kw = dict(prec=prec)
-    kw.update(autotune.tuned_options(prec, [molgen.nbf_sto3g(z) for z, _ in mols]))
+    if args.basis == "6-31g":
+        kw["basis"] = ks.KS_BASIS_631G
+    else:
+        kw.update(autotune.tuned_options(prec, [molgen.nbf_sto3g(z) for z, _ in mols]))
     if args.jk_chunks:
         kw["jk_chunks"] = args.jk_chunks
     if args.xc_chunks:
@@ -278,7 +287,8 @@ def main():
     ks.load()
     heavy = heavy_range(args.heavy)
     t_gen = time.perf_counter()
-    mols = molgen.batch(args.n_mol, args.seed, heavy)
+    mols = (molgen.batch_without(args.n_mol, args.seed, heavy) if args.basis == "6-31g"
+            else molgen.batch(args.n_mol, args.seed, heavy))
     print("generated %d molecules in %.1f s" % (len(mols), time.perf_counter() - t_gen), file=sys.stderr, flush=True)
 
     main_prec = ks.KS_FP64 if args.fp64_only else ks.KS_MIXED
@@ -371,10 +381,11 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "batch of %d synthetic saturated-tree molecules, %s heavy atoms {C,N,O,F}+H, "
-                               "B3LYP/STO-3G, grid %s per atom with Becke weights, DIIS(8), "
+                               "B3LYP/%s, grid %s per atom with Becke weights, DIIS(8), "
                                "converged at dE<1e-9 Ha & commutator<1e-7 (FP64) or dE<1e-6 Ha & "
                                "commutator<1e-5 (mixed)%s%s"
-                               % (args.n_mol, args.heavy, "x".join(str(v) for v in grid_shape(args)),
+                               % (args.n_mol, args.heavy, "6-31G" if args.basis == "6-31g" else "STO-3G",
+                                  "x".join(str(v) for v in grid_shape(args)),
                                   ", integral-direct J/K" if args.direct else "",
                                   ", Schwarz screening %g" % args.schwarz_tol if args.schwarz_tol > 0 else ""),
                    "n_mol": args.n_mol, "seed": args.seed,

@@ -284,6 +284,22 @@ def batch(n_mol: int, seed: int, n_heavy=9, start: int = 0):
     return out
 
 
+def batch_without(n_mol: int, seed: int, n_heavy=9, exclude=(9,)):
+    """Like batch(), with every molecule that contains an element of exclude
+    replaced by the first later tree of its own size that does not (for
+    bases that cover fewer elements, e.g. 6-31G here: H, C, N, O)."""
+    out = []
+    for i in range(n_mol):
+        if isinstance(n_heavy, tuple):
+            lo, hi = n_heavy
+            n = lo + _rng(seed + 0x5151, i).randint(hi - lo + 1)
+        else:
+            n = n_heavy
+        z, x, _ = tree_without(n, seed, i, exclude)
+        out.append((z, x))
+    return out
+
+
 def bonds(Z, xyz):
     """Bond list of a generated tree from its distances: heavy-heavy pairs
     within 1.7 A and H-heavy pairs within 1.25 A (the generator places them at
