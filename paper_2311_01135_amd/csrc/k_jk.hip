@@ -100,9 +100,89 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
     }
 }
 
+// Large molecules (partials in global memory): the work group walks its
+// quartet range one bra pair at a time, the kets of a bra being consecutive
+// quartets (coalesced integral reads).  Per bra the density rows of its two
+// shells are staged in LDS (Prow), the K rows of those shells (K_ac, K_ad,
+// K_bc, K_bd) accumulate in LDS (Krow) and J_ab in registers; both are added
+// to the partials once per bra, so only J_cd reaches global memory per
+// quartet.
+template <int LA, int LB, int LC, int LD, typename S>
+__device__ __forceinline__ void digest_class_rows(const JkArgs& g, const MolDesc& md, int chunk, int nchunk,
+                                                  const double* __restrict__ Pg, double* AJ, double* AK,
+                                                  double* Prow, double* Krow)
+{
+    constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
+    constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
+    constexpr int NCOMP = NA * NB * NC * ND;
+    const int N = md.nbf;
+    const long nq = md.nq[C];
+    const long lo = nq * chunk / nchunk, hi = nq * (chunk + 1) / nchunk;
+    if (lo >= hi) return;
+    const S* __restrict__ eri = (const S*)g.eri[C];
+    const long NQ = g.nq[C];
+    const int2* __restrict__ pb = g.pao[class_bra(C)] + md.pair0[class_bra(C)];
+    const int2* __restrict__ pk = g.pao[class_ket(C)] + md.pair0[class_ket(C)];
+    const int nket = md.npair[class_ket(C)];
+    int i, j0;
+    decode_quartet_jk(C, lo, nket, i, j0);
+    for (long q = lo; q < hi; i++, j0 = 0) {
+        const int nk = class_tri(C) ? i + 1 : nket;
+        const int seg = (int)min((long)(nk - j0), hi - q);
+        const long qbase = md.q0[C] + q;      // batch-global index of ket j0
+        q += seg;
+        const int2 A1 = pb[i];
+        const int oa = A1.x & 0xffff, ob = A1.y;
+        const bool same = (A1.x >> 16) != 0;
+        for (int t = threadIdx.x; t < (NA + NB) * N; t += blockDim.x) {
+            const int r = t / N, col = t % N;
+            Prow[t] = Pg[(r < NA ? oa + r : ob + r - NA) * N + col];
+            Krow[t] = 0.0;
+        }
+        __syncthreads();
+        double pab[NA][NB], jab[NA][NB];
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                pab[a][b] = Prow[a * N + ob + b];
+                jab[a][b] = 0.0;
+            }
+        for (int t = threadIdx.x; t < seg; t += blockDim.x) {
+            const int j = j0 + t;
+            const int2 A2 = pk[j];
+            double I[NCOMP];
+#pragma unroll
+            for (int k = 0; k < NCOMP; k++) I[k] = double(eri[(size_t)k * NQ + qbase + t]);
+            double f = same ? 0.5 : 1.0;
+            if (A2.x >> 16) f *= 0.5;
+            if (class_tri(C) && i == j) f *= 0.5;
+            jk_scatter_rows<NA, NB, NC, ND, double>(I, A2.x & 0xffff, A2.y, f, N, Prow, Prow + NA * N, Pg, pab, jab,
+                                                    AJ, Krow, Krow + NA * N);
+        }
+#pragma unroll
+        for (int a = 0; a < NA; a++)
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                double v = jab[a][b];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                if ((threadIdx.x & 63) == 0 && v != 0.0) lds_add(&AJ[(oa + a) * N + ob + b], v);
+            }
+        __syncthreads();
+        // a same-shell pair's b rows are its a rows
+        for (int t = threadIdx.x; t < (same ? NA : NA + NB) * N; t += blockDim.x) {
+            const int r = t / N, col = t % N;
+            const double v = same ? Krow[t] + Krow[t + NA * N] : Krow[t];
+            if (v != 0.0) lds_add(&AK[(r < NA ? oa + r : ob + r - NA) * N + col], v);
+        }
+        __syncthreads();
+    }
+}
+
 // GLOBAL (molecules whose 3 N^2 accumulators exceed the LDS): the density
-// is read from dP and the scatter goes to this item's partial matrices in
-// global memory with atomics (A = double).
+// is read from dP and the partials of this item are in global memory
+// (A = double), digested bra by bra (digest_class_rows).
 template <typename S, typename A, bool GLOBAL>
 __global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
 {
@@ -135,6 +215,18 @@ __global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
         Ps = Pl;
     }
     __syncthreads();
+    if constexpr (GLOBAL) {
+        static_assert(std::is_same<A, double>::value, "global partials are FP64");
+        double* Prow = (double*)smem_jk;          // [6][N]
+        double* Krow = Prow + 6 * N;              // [6][N]
+        digest_class_rows<0, 0, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+        digest_class_rows<1, 0, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+        digest_class_rows<1, 0, 1, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+        digest_class_rows<1, 1, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+        digest_class_rows<1, 1, 1, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+        digest_class_rows<1, 1, 1, 1, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+        return;
+    }
     digest_class<0, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
     digest_class<1, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
     digest_class<1, 0, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
@@ -218,9 +310,9 @@ bool jk_acc_fp64(const ks_batch* b) { return jk_mode(b) != 1; }
 size_t jk_lds_bytes(const ks_batch* b)
 {
     const int mode = jk_mode(b);
-    if (mode == 2) return 0;
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
+    if (mode == 2) return 12 * (size_t)maxn * sizeof(double);   // density and K rows of one bra
     return 3 * (size_t)maxn * maxn * (mode == 0 ? sizeof(double) : sizeof(float));
 }
 
