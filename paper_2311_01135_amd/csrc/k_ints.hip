@@ -325,15 +325,17 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
 #pragma unroll
             for (int jp = 0; jp < PP; jp++) ket(jp);
         } else {
+            const int nk = sc.np * sd.np;       // the ket's real primitive pairs
 #pragma unroll 1
-            for (int jp = 0; jp < PP; jp++) ket(jp);
+            for (int jp = 0; jp < nk; jp++) ket(jp);
         }
     };
     if constexpr (PP <= kNPrimPair) {
         for (int ip = 0; ip < PP; ip++) bra(ip);
     } else {
+        const int nb = sa.np * sb.np;
 #pragma unroll 1
-        for (int ip = 0; ip < PP; ip++) bra(ip);
+        for (int ip = 0; ip < nb; ip++) bra(ip);
     }
 }
 
@@ -435,21 +437,22 @@ __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
 // Primitive-pair tables of every shell pair of one pair class, stored
 // field-major [f][k][pair] (f = p, Px, Py, Pz, K; k = primitive pair) so that
 // lanes working on consecutive pairs load consecutive addresses.
-// pp primitive pairs per shell pair: pp = 9 holds 3 x 3, pp = 36 holds
-// 6 x 6 with the pairs beyond a shell's primitive count padded with zero
-// weight (K = 0, p = 1, P = A), which every integral loop skips.
+// pp primitive pairs per shell pair: entry k = ka nb + kb for the na x nb
+// primitive pairs of the two shells (pp = 9: always 3 x 3); with pp = 36
+// (6-31G) the entries from na nb on are padding (K = 0, p = 1, P = A), which
+// the integral loops do not visit.
 __global__ void pair_kernel(const Shell* __restrict__ shells, const Pair* __restrict__ pairs, long npair, int pp,
                             double* __restrict__ out)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npair * pp) return;
     const long ip = t / pp;
-    const int per = pp == kNPrimPair ? kNPrim : kPrimMax;
-    const int k = (int)(t % pp), ka = k / per, kb = k % per;
+    const int k = (int)(t % pp);
     const Pair pr = pairs[ip];
     const Shell& A = shells[pr.sa];
     const Shell& B = shells[pr.sb];
-    if (ka >= A.np || kb >= B.np) {
+    const int ka = k / B.np, kb = k % B.np;
+    if (k >= A.np * B.np) {
         for (int d = 0; d < 3; d++) out[((size_t)(1 + d) * pp + k) * npair + ip] = A.A[d];
         out[(size_t)k * npair + ip] = 1.0;
         out[((size_t)4 * pp + k) * npair + ip] = 0.0;
