@@ -388,52 +388,40 @@ struct EriArgs {
     double schwarz;         // quartets with Q_ab Q_cd below this are stored as 0 (0 = off)
 };
 
-// Each work group of kEriThreads threads takes kEriQpt consecutive blocks of
-// quartets (one quartet per thread per block) and first copies the Boys row
-// table of this class's total angular momentum (23 KB) into LDS, where the
-// per-lane reads of the Boys interpolation are served at LDS latency.
-// (Measured on 2048 molecules: 544 ms with the global table and one quartet
-// per thread, 461 ms this way; persistent groups were slower beside the grid
-// kernel on the other stream.)
-constexpr int kEriThreads = 256, kEriQpt = 4;
+// One thread per contracted quartet; the Boys interpolation reads the full
+// table from global memory (L1/L2).  (A copy of the row table in LDS per
+// group made the class kernels 15% faster alone, but beside the grid kernel
+// on the other stream the two compete for LDS and the pair finished no
+// earlier.)
+constexpr int kEriThreads = 128;
 
 template <int LA, int LB, int LC, int LD, typename R, typename S, int PP>
 __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
 {
     constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
     constexpr int NCOMP = class_ncomp(C);
-    constexpr int L = LA + LB + LC + LD;
     static_assert(std::is_same<R, double>::value, "integrals are evaluated in FP64");
-    __shared__ __align__(16) double rows[kBoysNTR * kBoysKR];
-    {
-        const double2* src = (const double2*)(g.rows + (size_t)L * kBoysNTR * kBoysKR);
-        for (int t = threadIdx.x; t < kBoysNTR * kBoysKR / 2; t += blockDim.x) ((double2*)rows)[t] = src[t];
-    }
-    __syncthreads();
+    const long qg = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qg >= g.nq) return;
     S* out = (S*)g.out;
-    const long base = (long)blockIdx.x * kEriThreads * kEriQpt;
-    for (int r = 0; r < kEriQpt; r++) {
-        const long qg = base + (long)r * kEriThreads + threadIdx.x;
-        if (qg >= g.nq) break;
-        const int m = find_mol(g.qoff, g.n_mol, qg);
-        const MolDesc& md = g.mol[m];
-        const long q = qg - g.qoff[m];
-        int i, j;
-        decode_quartet(C, q, md.npair[class_ket(C)], i, j);
-        const int ib = md.pair0[class_bra(C)] + i, ik = md.pair0[class_ket(C)] + j;
-        if (g.schwarz > 0.0 && g.Qb[ib] * g.Qk[ik] < g.schwarz) {
+    const int m = find_mol(g.qoff, g.n_mol, qg);
+    const MolDesc& md = g.mol[m];
+    const long q = qg - g.qoff[m];
+    int i, j;
+    decode_quartet(C, q, md.npair[class_ket(C)], i, j);
+    const int ib = md.pair0[class_bra(C)] + i, ik = md.pair0[class_ket(C)] + j;
+    if (g.schwarz > 0.0 && g.Qb[ib] * g.Qk[ik] < g.schwarz) {
 #pragma unroll
-            for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = S(0);
-            continue;
-        }
-        const Pair P1 = g.pb[ib], P2 = g.pk[ik];
-        const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
-        R acc[NCOMP];
-        const PairView<PP> vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
-        eri_quartet<LA, LB, LC, LD, R, true, PP>(sa, sb, sc, sd, vb, vk, rows, R(g.cut), acc);
-#pragma unroll
-        for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
+        for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = S(0);
+        return;
     }
+    const Pair P1 = g.pb[ib], P2 = g.pk[ik];
+    const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
+    R acc[NCOMP];
+    const PairView<PP> vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
+    eri_quartet<LA, LB, LC, LD, R, false, PP>(sa, sb, sc, sd, vb, vk, (const R*)g.tab, R(g.cut), acc);
+#pragma unroll
+    for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
 }
 
 // Primitive-pair tables of every shell pair of one pair class, stored
@@ -951,9 +939,7 @@ static ks_status launch_class(ks_batch* b, int c)
     g.Qb = b->d_Q[class_bra(c)];
     g.Qk = b->d_Q[class_ket(c)];
     g.schwarz = b->schwarz_done ? b->opt.schwarz_tol : 0.0;
-    g.rows = b->d_boys_rows;
-    const long per = (long)kEriThreads * kEriQpt;
-    const long nb = (g.nq + per - 1) / per;
+    const long nb = (g.nq + kEriThreads - 1) / kEriThreads;
     hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S, PP>), dim3((unsigned)nb), dim3(kEriThreads), 0,
                        b->stream, g);
     KS_HIP(hipGetLastError());
