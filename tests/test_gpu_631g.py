@@ -127,3 +127,35 @@ def test_direct_631g(ks, refs):
 def test_631g_rejects_fluorine(ks):
     with pytest.raises(ks.KsError):
         ks.Batch([(np.array([9, 1]), np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.92]]))], basis=ks.KS_BASIS_631G)
+
+
+def test_631g_server_equals_batch(ks):
+    # the continuous-batching server with the 6-31G basis: each result equals
+    # the molecule solved alone in a batch (FP64, same kernels)
+    mols = _mols()
+    alone = []
+    for z, x in mols:
+        with ks.Batch([(z, x)], basis=ks.KS_BASIS_631G, jk_chunks=8, xc_chunks=16) as b:
+            b.scf_solve()
+            alone.append(b.result(0))
+    with ks.Server(max_batch=2, basis=ks.KS_BASIS_631G) as s:
+        tickets = [s.submit(z, x) for z, x in mols]
+        for _ in range(400):
+            s.progress()
+            if s.stats()["done"] == len(mols):
+                break
+        served = [s.poll(t) for t in tickets]
+    for a, r in zip(alone, served):
+        assert r is not None
+        assert abs(r["E"] - a["E"]) <= 1e-10 and abs(r["gap"] - a["gap"]) <= 1e-10
+
+
+def test_631g_graphs(ks, refs):
+    # graph-replayed iterations with the 36-entry pair tables
+    mols = _mols()
+    s = torch.cuda.Stream()
+    with ks.Batch(mols, basis=ks.KS_BASIS_631G, graphs=1, stream=s.cuda_stream) as b:
+        b.scf_solve()
+        for m, ref in enumerate(refs):
+            r = b.result(m)
+            assert r["status"] == 1 and abs(r["E"] - ref["E"]) <= 1e-8, (m, r["E"], ref["E"])
