@@ -76,6 +76,11 @@ def test_rejects_bad_options(lib):
     assert st == -1 and "schwarz_tol" in err
     st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], graphs=3)
     assert st == -1 and "graphs" in err
+    st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], basis=2)
+    assert st == -1 and "basis" in err
+    # 6-31G covers H, C, N, O: fluorine is rejected before any device work
+    st, h, err = _create(lib, [9, 1], [[0, 0, 0], [0, 0, 0.92]], basis=1)
+    assert st == -1 and "6-31G" in err
 
 
 def test_rejects_too_large_fp64(lib):
