@@ -91,6 +91,18 @@ def test_rejects_too_large_fp64(lib):
     assert st == -5 and "basis functions" in err
 
 
+def test_rejects_beyond_mixed_limit(lib):
+    # 45 carbon atoms on a line: 225 basis functions, one past the mixed
+    # path's 224 (in 6-31G, 9 per atom: 405); molecules of exactly 224 run
+    # in the GPU tests
+    z = [6] * 45
+    x = [[1.5 * k, 0.0, 0.0] for k in range(45)]
+    st, h, err = _create(lib, z, x, prec=1)
+    assert st == -5 and "225 basis functions" in err
+    st, h, err = _create(lib, z, x, prec=1, basis=1)
+    assert st == -5 and "405 basis functions" in err
+
+
 def test_null_handle_calls(lib):
     assert lib.eri_build(None) == -1
     assert lib.scf_solve(None) == -1

@@ -554,6 +554,22 @@ def test_hf_energy_rotation_invariant():
     assert abs(e1 - e2) < 1e-10
 
 
+def test_b3lyp_size_consistency():
+    # the restricted KS energy of closed-shell fragments far apart is the sum
+    # of fragment energies; HOMO and LUMO are the extreme fragment values
+    # (water and methane 100 angstrom apart: the dipole-induced terms are
+    # below 1e-7 Ha at R = 189 bohr)
+    (zw, xw), (zm, xm) = molgen.water(0), molgen.tree(1, 0, 0)
+    rw, rm = O.Mol(zw, xw).scf(xc=O.XC_B3LYP), O.Mol(zm, xm).scf(xc=O.XC_B3LYP)
+    z = np.concatenate([zw, zm])
+    x = np.concatenate([np.asarray(xw) - np.mean(xw, axis=0), np.asarray(xm) - np.mean(xm, axis=0) + [100.0, 0, 0]])
+    r = O.Mol(z, x).scf(xc=O.XC_B3LYP)
+    assert r["status"] == rw["status"] == rm["status"] == 1
+    assert abs(r["E"] - (rw["E"] + rm["E"])) < 1e-7
+    assert abs(r["homo"] - max(rw["homo"], rm["homo"])) < 1e-6
+    assert abs(r["lumo"] - min(rw["lumo"], rm["lumo"])) < 1e-6
+
+
 def test_rejects_invalid_input():
     with pytest.raises(ValueError):
         O.Mol([1], np.zeros((1, 3)))                      # odd electron count
