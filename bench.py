@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--xc-chunks", type=int, default=0)
     p.add_argument("--serve-requests", type=int, default=512, help="serving leg requests (0 = skip)")
     p.add_argument("--grid", type=str, default="50,12,24", help="radial,theta,phi points per atom")
+    p.add_argument("--coarse-grid", type=str, default="25,8,16",
+                   help="radial,theta,phi of the coarse start grid (0,0,0 = none); results stay the main grid's")
     p.add_argument("--direct", action="store_true", help="integral-direct J/K (ERIs recomputed every iteration)")
     p.add_argument("--schwarz-tol", type=float, default=0.0, help="Schwarz screening threshold (0 = off)")
     p.add_argument("--basis", choices=["sto-3g", "6-31g"], default="sto-3g",
@@ -71,9 +73,13 @@ def heavy_range(s):
     return int(s)
 
 
-def xc_flops(nbf, ngrid, niter):
-    """Algorithmic XC GEMM flops: 2 G N^2 for X = Phi P plus 2 G N^2 for Phi^T W, per iteration."""
-    return float(sum(4.0 * g * n * n * it for n, g, it in zip(nbf, ngrid, niter)))
+def xc_flops(nbf, ngrid, niter, ngridc=None, ncoarse=None):
+    """Algorithmic XC GEMM flops: 2 G N^2 for X = Phi P plus 2 G N^2 for Phi^T W, per iteration
+    (G of the coarse start grid for the iterations that ran on it)."""
+    ngridc = ngridc or [0] * len(nbf)
+    ncoarse = ncoarse or [0] * len(nbf)
+    return float(sum(4.0 * n * n * (g * (it - ic) + gc * ic)
+                     for n, g, it, gc, ic in zip(nbf, ngrid, niter, ngridc, ncoarse)))
 
 
 def measured_traffic(args, prec_name):
@@ -88,7 +94,8 @@ def measured_traffic(args, prec_name):
         sha = hashlib.sha256(f.read()).hexdigest()
     w = t.get("workload", {})
     if (t.get("source_sha256") != sha or w.get("n_mol") != args.n_mol or w.get("seed") != args.seed
-            or w.get("heavy") != args.heavy or w.get("precision") != prec_name):
+            or w.get("heavy") != args.heavy or w.get("precision") != prec_name
+            or w.get("coarse_grid", "0,0,0") != args.coarse_grid):
         return None
     # the counters were taken on the default STO-3G, stored-integral, 50x12x24 workload
     if args.basis != "sto-3g" or args.direct or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24):
@@ -151,6 +158,7 @@ def solve_batch(ks, mols, prec, timing, args):
     if args.xc_chunks:
         kw["xc_chunks"] = args.xc_chunks
     kw["n_rad"], kw["n_theta"], kw["n_phi"] = grid_shape(args)
+    kw.update(coarse_options(args))
     if args.direct:
         kw["direct"] = 1
     if args.schwarz_tol > 0:
@@ -160,6 +168,8 @@ def solve_batch(ks, mols, prec, timing, args):
         b.set_timing(True)
     b.scf_solve()
     res = [b.result(m) for m in range(b.n_mol)]
+    for m, r in enumerate(res):
+        r["n_coarse"] = b.iterations(m)[1]
     return b, res
 
 
@@ -186,10 +196,15 @@ def run_path(ks, torch, mols, prec, args, steps, warmup):
     return total, times, last
 
 
-def serve_run(ks, reqs, arrivals, prec):
+def coarse_options(args):
+    r, t, f = (int(v) for v in args.coarse_grid.split(","))
+    return dict(coarse_rad=r, coarse_theta=t, coarse_phi=f)
+
+
+def serve_run(ks, reqs, arrivals, prec, **options):
     """Drive a ks.Server with requests arriving at the given times (s); returns
     (wall seconds, latencies from scheduled arrival to observed completion)."""
-    srv = ks.Server(prec=prec)
+    srv = ks.Server(prec=prec, **options)
     n = len(reqs)
     lat = np.zeros(n)
     pending = {}
@@ -220,17 +235,17 @@ def serve_run(ks, reqs, arrivals, prec):
 
 
 def serving_leg(ks, args):
-    """configs[3]-shaped serving: 3-11 heavy atoms, mixed precision; saturated
+    """Serving workload: 3-11 heavy atoms, mixed precision; saturated
     throughput first, then Poisson arrivals at 0.8 x that rate."""
     from paper_2311_01135_amd import molgen
     n = args.serve_requests
     reqs = molgen.batch(n, 3, (3, 11))
-    wall_sat, _ = serve_run(ks, reqs, np.zeros(n), ks.KS_MIXED)
+    wall_sat, _ = serve_run(ks, reqs, np.zeros(n), ks.KS_MIXED, **coarse_options(args))
     sat = n / wall_sat
     lam = 0.8 * sat
     rng = np.random.default_rng(3)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
-    wall, lat = serve_run(ks, reqs, arrivals, ks.KS_MIXED)
+    wall, lat = serve_run(ks, reqs, arrivals, ks.KS_MIXED, **coarse_options(args))
     return dict(requests=n, heavy_atoms="3-11", precision="mixed", saturated_solves_per_s=sat,
                 arrival_rate_per_s=lam, solves_per_s=n / wall, p50_latency_s=float(np.percentile(lat, 50)),
                 p99_latency_s=float(np.percentile(lat, 99)), max_latency_s=float(lat.max()))
@@ -298,6 +313,9 @@ def main():
     value = args.n_mol * args.steps / total
     print("main path: %.2f solves/s, %.2f s/step" % (value, total / args.steps), file=sys.stderr, flush=True)
     niter = [r["n_iter"] for r in res]
+    ncoarse = [r["n_coarse"] for r in res]
+    cg = [int(v) for v in args.coarse_grid.split(",")]
+    ngridc = [n * cg[0] * cg[1] * cg[2] for n in info["n_atoms"]]
     status = [r["status"] for r in res]
 
     fp64 = None
@@ -323,7 +341,7 @@ def main():
 
     # roofline of the XC kernel (dominant), from the last timed step
     xc_ms, xc_launches = kt.get("xc", (float("nan"), 0))
-    fl = xc_flops(info["nbf"], info["ngrid"], niter)
+    fl = xc_flops(info["nbf"], info["ngrid"], niter, ngridc, ncoarse)
     achieved = fl / max(1, xc_launches) / (xc_ms * 1e-3) / 1e12 if xc_launches else float("nan")
     dtype = "f64" if main_prec == ks.KS_FP64 else "f32"
     roof = dict(bound="mfma", kernel="xc_kernel", achieved=achieved, peak=PEAK[dtype], unit="TFLOP/s",
@@ -383,16 +401,20 @@ def main():
         "config": {"workload": "batch of %d synthetic saturated-tree molecules, %s heavy atoms {C,N,O,F}+H, "
                                "B3LYP/%s, grid %s per atom with Becke weights, DIIS(8), "
                                "converged at dE<1e-9 Ha & commutator<1e-7 (FP64) or dE<1e-6 Ha & "
-                               "commutator<1e-5 (mixed)%s%s"
+                               "commutator<1e-5 (mixed) on that grid%s%s%s"
                                % (args.n_mol, args.heavy, "6-31G" if args.basis == "6-31g" else "STO-3G",
                                   "x".join(str(v) for v in grid_shape(args)),
+                                  "" if args.coarse_grid == "0,0,0" else
+                                  ", SCF started on a %s coarse grid" % args.coarse_grid.replace(",", "x"),
                                   ", integral-direct J/K" if args.direct else "",
                                   ", Schwarz screening %g" % args.schwarz_tol if args.schwarz_tol > 0 else ""),
                    "n_mol": args.n_mol, "seed": args.seed,
                    "nbf_range": [min(info["nbf"]), max(info["nbf"])],
                    "grid_points": int(sum(info["ngrid"])),
+                   "coarse_grid": args.coarse_grid,
                    "precision": "mixed: ERI/JK/XC FP32, Loewdin/eigh/DIIS/energy FP64" if dtype == "f32" else "fp64"},
-        "iterations": {"mean": float(np.mean(niter)), "max": int(max(niter))},
+        "iterations": {"mean": float(np.mean(niter)), "max": int(max(niter)),
+                       "coarse_grid_mean": float(np.mean(ncoarse))},
         "unconverged": int(sum(s != 1 for s in status)),
         "kernel_rates": rates,
         "kernel_ms_avg": {k: v[0] for k, v in kt.items()},

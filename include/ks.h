@@ -88,6 +88,15 @@ typedef struct {
     int graphs;             /* 1: from the second SCF iteration on, scf_step / scf_solve replay one
                                iteration's launches as a captured HIP graph (needs a non-NULL stream at
                                ks_batch_create; ignored while kernel timing is on).  0 = plain launches */
+    int coarse_rad, coarse_theta, coarse_phi;
+                            /* optional coarse-grid start (all three > 0 to enable, 0 = off): every
+                               molecule begins its SCF with XC on a coarse_rad x coarse_theta x coarse_phi
+                               grid per atom and moves to the main grid once |dE| < 1e-4 Ha and the
+                               commutator < 1e-3 there (or after 12 iterations).  DIIS keeps its history
+                               across the move; convergence is only tested on the main grid, from its
+                               second iteration, so results are those of the main grid.  Each count at
+                               most the main grid's.  Measured best for 9-11-heavy-atom molecules on the
+                               50 x 12 x 24 grid: 25 x 8 x 16. */
 } ks_options;
 
 /* Initial density.  The paper only says C_1 is initialised (section 3.1).
@@ -208,6 +217,11 @@ ks_status ks_get_grid(const ks_batch* b, int mol, double* out);
  * the last Fock build, its change from the previous iteration and the max
  * norm of the orthogonalised commutator X^T (FPS - SPF) X. */
 ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, double* err);
+
+/* Iterations of molecule mol so far: all of them (*n_iter) and those whose XC
+ * ran on the coarse start grid (*n_coarse; 0 without one).  Either pointer
+ * may be NULL. */
+ks_status ks_get_iterations(const ks_batch* b, int mol, int* n_iter, int* n_coarse);
 
 /* Kernel timing.  ks_set_timing(b, 1) clears the counters and records a pair
  * of HIP events on the batch stream around every launch of each kernel

@@ -402,6 +402,14 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         set_error("grid sizes, max_iter >= 1, 1 <= diis_space <= %d and positive tolerances required", kMaxDiis);
         return KS_EINVAL;
     }
+    {
+        const int cr = opt.coarse_rad, ct = opt.coarse_theta, cp = opt.coarse_phi;
+        const bool off = cr == 0 && ct == 0 && cp == 0;
+        if (!off && (cr < 1 || ct < 1 || cp < 1 || cr > opt.n_rad || ct > opt.n_theta || cp > opt.n_phi)) {
+            set_error("coarse grid: all of coarse_rad, coarse_theta, coarse_phi 0 (off) or each in 1..the main grid's count");
+            return KS_EINVAL;
+        }
+    }
     if (opt.prec == KS_MIXED) {
         opt.e_tol = std::max(opt.e_tol, kMixedETol);
         opt.comm_tol = std::max(opt.comm_tol, kMixedCommTol);
@@ -531,6 +539,18 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     }
     b->nmat = mat0;
     b->ngrid = grid0;
+    // the coarse start grids follow the main grids in the batch grid array
+    b->coarse = opt.xc != KS_XC_HF && opt.coarse_rad > 0;
+    if (b->coarse) {
+        const long per_atom_c = (long)opt.coarse_rad * opt.coarse_theta * opt.coarse_phi;
+        long gc = grid0;
+        for (auto& md : b->mol) {
+            md.gridc0 = gc;
+            md.ngridc = (long)md.natom * per_atom_c;
+            gc += md.ngridc;
+        }
+        b->ngridc = gc - grid0;
+    }
     for (int c = 0; c < 3; c++) b->npairs[c] = (long)pairs[c].size();
     for (int c = 0; c < kNClass; c++) b->nq[c] = qoff[c];
 
@@ -557,6 +577,24 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         }
     }
     xc_first.push_back((int)b->xc_items.size());
+    std::vector<int> xc_first_c;
+    if (b->coarse) {
+        for (int m = 0; m < n_mol; m++) {
+            xc_first_c.push_back((int)b->xc_items.size());
+            const MolDesc& md = b->mol[m];
+            const long nfull = xc_first[m + 1] - xc_first[m];
+            const long nch = std::max(1L, std::min(nfull, md.ngridc / (4L * bp)));
+            for (long c = 0; c < nch; c++) {
+                XcItem it{};
+                it.mol = m;
+                it.stage = 1;
+                it.g0 = md.gridc0 - md.grid0 + md.ngridc * c / nch;
+                it.g1 = md.gridc0 - md.grid0 + md.ngridc * (c + 1) / nch;
+                b->xc_items.push_back(it);
+            }
+        }
+        xc_first_c.push_back((int)b->xc_items.size());
+    }
 
     // device memory
     ks_status st;
@@ -587,6 +625,14 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
     if ((st = upload(b, &b->d_boys_rows, boys_rows))) return st;
     if ((st = upload(b, &b->d_radial, rad))) return st;
     if ((st = upload(b, &b->d_ang, ang))) return st;
+    if (b->coarse) {
+        std::vector<double> radc, angc;
+        radial_rule(opt.coarse_rad, radc);
+        gauss_legendre(opt.coarse_theta, angc);
+        if ((st = upload(b, &b->d_radial_c, radc))) return st;
+        if ((st = upload(b, &b->d_ang_c, angc))) return st;
+        if ((st = upload(b, &b->d_xc_first_c, xc_first_c))) return st;
+    }
     if ((st = upload(b, &b->d_ptoff, ptoff))) return st;
     if ((st = upload(b, &b->d_jk_items, b->jk_items))) return st;
     if ((st = upload(b, &b->d_xc_items, b->xc_items))) return st;
@@ -606,6 +652,10 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         if ((st = upload(b, &b->d_qoff[c], qprefix[c]))) return st;
     std::vector<MolState> s0(n_mol);
     std::memset(s0.data(), 0, sizeof(MolState) * n_mol);
+    for (auto& x : s0) {
+        x.stage = b->coarse ? 1 : 0;
+        x.it_full = 1;
+    }
     if ((st = upload(b, &b->d_state, s0))) return st;
     double** mats[] = {&b->d_S, &b->d_T, &b->d_V, &b->d_H, &b->d_X, &b->d_F, &b->d_P,
                        &b->d_J, &b->d_K, &b->d_Vxc, &b->d_Fp, &b->d_C, &b->d_Pprev, &b->d_Cp};
@@ -697,7 +747,7 @@ ks_status ks_setup(ks_batch* b)
             return KS_EINVAL;
         }
     if (b->opt.xc != KS_XC_HF) {
-        if ((st = dev_alloc(b, &b->d_grid, 4 * (size_t)b->ngrid))) return st;
+        if ((st = dev_alloc(b, &b->d_grid, 4 * (size_t)(b->ngrid + b->ngridc)))) return st;
         KS_HIP(hipEventRecord(b->ev_main, b->stream));
         KS_HIP(hipStreamWaitEvent(b->aux, b->ev_main, 0));
         if ((st = launch_grid(b, b->aux))) return st;
@@ -1084,6 +1134,21 @@ ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, 
     if (E) *E = s.E;
     if (dE) *dE = s.E - s.Eprev;
     if (err) *err = s.err;
+    return KS_OK;
+}
+
+ks_status ks_get_iterations(const ks_batch* b, int mol, int* n_iter, int* n_coarse)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol) {
+        set_error("molecule index %d out of range", mol);
+        return KS_EINVAL;
+    }
+    MolState s;
+    KS_HIP(hipMemcpyAsync(&s, b->d_state + mol, sizeof(MolState), hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    if (n_iter) *n_iter = s.iter;
+    if (n_coarse) *n_coarse = s.stage ? s.iter : s.it_full - 1;
     return KS_OK;
 }
 

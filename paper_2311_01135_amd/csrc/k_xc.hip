@@ -45,10 +45,11 @@ __device__ __forceinline__ T becke_f3(T mu)
 template <typename T>
 __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mols, const double* __restrict__ Rat,
                                                   const double* __restrict__ radial, const double* __restrict__ ang,
-                                                  int nrad, int nth, int nph, double* __restrict__ out)
+                                                  int nrad, int nth, int nph, int coarse, double* __restrict__ out)
 {
     const int m = blockIdx.y;
     const MolDesc md = mols[m];
+    const long base = coarse ? md.gridc0 : md.grid0, ng = coarse ? md.ngridc : md.ngrid;
     const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
     extern __shared__ double smem_grid[];
     const int na = md.natom;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
         invR[i] = a == c ? T(0) : T(1.0 / sqrt(dx * dx + dy * dy + dz * dz));
     }
     __syncthreads();
-    if (l >= md.ngrid) return;
+    if (l >= ng) return;
     const int per_atom = nrad * nth * nph;
     const int A = (int)(l / per_atom);
     int rem = (int)(l % per_atom);
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
         den += Pa;
     }
     const double w = radial[nrad + i] * ang[nth + j] * (2.0 * kPi / nph) * ((double)num / (double)den);
-    double* o = out + 4 * (md.grid0 + l);
+    double* o = out + 4 * (base + l);
     o[0] = p[0];
     o[1] = p[1];
     o[2] = p[2];
@@ -106,12 +107,12 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
 }
 
 template <typename T>
-static ks_status run_grid(ks_batch* b, hipStream_t s)
+static ks_status run_grid(ks_batch* b, hipStream_t s, bool coarse)
 {
     long maxg = 0;
     int maxat = 0;
     for (auto& m : b->mol) {
-        maxg = std::max(maxg, m.ngrid);
+        maxg = std::max(maxg, coarse ? m.ngridc : m.ngrid);
         maxat = std::max(maxat, m.natom);
     }
     int bs = 64;
@@ -125,16 +126,23 @@ static ks_status run_grid(ks_batch* b, hipStream_t s)
         return KS_EUNSUPPORTED;
     }
     KS_HIP(hipFuncSetAttribute((const void*)grid_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const ks_options& o = b->opt;
     hipLaunchKernelGGL(grid_kernel<T>, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, s,
-                       b->d_mol, b->d_R, b->d_radial, b->d_ang, b->opt.n_rad, b->opt.n_theta, b->opt.n_phi, b->d_grid);
+                       b->d_mol, b->d_R, coarse ? b->d_radial_c : b->d_radial, coarse ? b->d_ang_c : b->d_ang,
+                       coarse ? o.coarse_rad : o.n_rad, coarse ? o.coarse_theta : o.n_theta,
+                       coarse ? o.coarse_phi : o.n_phi, (int)coarse, b->d_grid);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }
 
+// The coarse start grid (when in use) first: the first iterations need only it.
 ks_status launch_grid(ks_batch* b, hipStream_t s)
 {
     KTimer tm(b, "grid", s);
-    return b->opt.prec == KS_MIXED ? run_grid<float>(b, s) : run_grid<double>(b, s);
+    ks_status st;
+    if (b->coarse && (st = b->opt.prec == KS_MIXED ? run_grid<float>(b, s, true) : run_grid<double>(b, s, true)))
+        return st;
+    return b->opt.prec == KS_MIXED ? run_grid<float>(b, s, false) : run_grid<double>(b, s, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,6 +557,8 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
     const XcItem it = g.items[blockIdx.x];
     const int m = it.mol;
     if (g.only_active && g.state[m].status != KS_MOL_ACTIVE) return;
+    // SCF iterations use the grid of the molecule's stage; direct calls the main grid
+    if (it.stage != (g.only_active ? g.state[m].stage : 0)) return;
     const MolDesc md = g.mol[m];
     const int N = md.nbf, NP = md.np, NT = NP >> 4, LDP = PGL ? NP : xc_ldp(NP), PL = NP * LDG;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -814,7 +824,8 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
 // V_XC = sum over the molecule's chunks of (A + A^T); E_XC = sum of chunk sums.
 template <typename T>
 __global__ void xc_reduce_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state,
-                                 const int* __restrict__ first, const T* __restrict__ part, long stride,
+                                 const int* __restrict__ first, const int* __restrict__ first_c,
+                                 const T* __restrict__ part, long stride,
                                  const double* __restrict__ part_exc, int only_active, double* __restrict__ V,
                                  double* __restrict__ exc)
 {
@@ -823,7 +834,8 @@ __global__ void xc_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
     const MolDesc md = mols[m];
     const int N = md.nbf, NP = md.np;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i0 = first[m], i1 = first[m + 1];
+    const int* fr = only_active && state[m].stage ? first_c : first;
+    const int i0 = fr[m], i1 = fr[m + 1];
     if (t == 0) {
         double s = 0.0, c = 0.0;
         for (int i = i0; i < i1; i++) {
@@ -950,7 +962,7 @@ static ks_status run_xc(ks_batch* b, const double* P, double* V, bool only_activ
     for (auto& m : b->mol) maxnn = std::max(maxnn, m.nbf * m.nbf);
     KTimer tr(b, "xc_reduce");
     hipLaunchKernelGGL(xc_reduce_kernel<T>, dim3((maxnn + 255) / 256, b->n_mol), dim3(256), 0, b->stream, b->d_mol,
-                       b->d_state, b->d_xc_first, (const T*)b->d_xc_part, g.part_stride, b->d_xc_exc,
+                       b->d_state, b->d_xc_first, b->d_xc_first_c, (const T*)b->d_xc_part, g.part_stride, b->d_xc_exc,
                        (int)only_active, V, b->d_exc);
     KS_HIP(hipGetLastError());
     return KS_OK;

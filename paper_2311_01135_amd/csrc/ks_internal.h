@@ -30,6 +30,11 @@ constexpr double kRhoCut = 1e-12;      // points below this density carry no XC
 // Fock matrix carries ~1e-6 noise, below which FP32 cannot resolve changes.
 constexpr double kMixedETol = 1e-6;
 constexpr double kMixedCommTol = 1e-5;
+// Coarse start grid (options coarse_*): a molecule moves to the main grid
+// once these hold on the coarse grid, or after kCoarseMaxIter iterations.
+constexpr double kCoarseETol = 1e-4;
+constexpr double kCoarseCommTol = 1e-3;
+constexpr int kCoarseMaxIter = 12;
 // Primitive ERI screening: a primitive quartet is skipped when its Gaussian
 // prefactor 2 pi^(5/2) K_ab K_cd / (p q sqrt(p + q)) is below the cut (far
 // below the FP64 parity tolerance, resp. the FP32 storage rounding).  kQMin
@@ -95,6 +100,7 @@ struct MolDesc {
     long mat0;              // element offset of this molecule's N x N blocks
     long grid0;             // first grid point
     long ngrid;
+    long gridc0, ngridc;    // the coarse start grid (ngridc = 0 without one)
     int pair0[3];           // first pair of each pair class in the class lists
     int npair[3];
     long q0[kNClass];       // first quartet of each class in the batch-global class list
@@ -109,7 +115,9 @@ struct MolState {
     int nhist;              // DIIS vectors held
     int head;               // DIIS ring position
     int final_;             // set when this iteration's F is the last one
-    int pad[3];
+    int stage;              // 1 while XC runs on the coarse start grid, then 0
+    int it_full;            // first iteration on the main grid (convergence is tested after it)
+    int pad;
     double E, Eprev, err;
     double Eterms[6];
     double B[kMaxDiis * kMaxDiis];   // DIIS overlaps of the held error vectors
@@ -118,8 +126,8 @@ struct MolState {
 // XC work item: a contiguous range of one molecule's grid points.
 struct XcItem {
     int mol;
-    int pad;
-    long g0, g1;
+    int stage;              // 0: main grid, 1: coarse start grid
+    long g0, g1;            // points md.grid0 + g0 .. md.grid0 + g1 - 1 of the batch grid
 };
 
 struct JkItem {
@@ -178,7 +186,11 @@ struct ks_batch {
     float* d_boys_f = nullptr;
     double* d_radial = nullptr;     // r_i, w_i (n_rad each)
     double* d_ang = nullptr;        // cos theta_j, w_j (n_theta each)
-    double* d_grid = nullptr;       // [ngrid][4]
+    double* d_grid = nullptr;       // [ngrid + ngridc][4]: main grids, then the coarse start grids
+    bool coarse = false;            // coarse start grid in use (options coarse_*)
+    long ngridc = 0;
+    double* d_radial_c = nullptr;   // coarse grid rules
+    double* d_ang_c = nullptr;
     // matrices (nmat doubles each)
     double *d_S = nullptr, *d_T = nullptr, *d_V = nullptr, *d_H = nullptr, *d_X = nullptr;
     double *d_F = nullptr, *d_P = nullptr, *d_J = nullptr, *d_K = nullptr, *d_Vxc = nullptr;
@@ -198,6 +210,7 @@ struct ks_batch {
     std::vector<ks::XcItem> xc_items;
     ks::XcItem* d_xc_items = nullptr;
     int* d_xc_first = nullptr;      // [n_mol + 1] first XC item of each molecule
+    int* d_xc_first_c = nullptr;    // [n_mol + 1] first coarse-grid XC item of each molecule
     void* d_xc_part = nullptr;      // [items][np^2 max]
     double* d_xc_exc = nullptr;     // [items]
     double* d_exc = nullptr;        // [n_mol]

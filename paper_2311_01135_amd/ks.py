@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", 
 
 EXPORTS = ["ks_default_options", "ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup",
            "eri_build", "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "scf_solve_many",
-           "ks_get_result", "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence", "ks_kernel_times",
+           "ks_get_result", "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence",
+           "ks_get_iterations", "ks_kernel_times",
            "ks_kernel_counts", "ks_set_timing",
            "ks_batch_destroy", "ks_last_error", "ks_server_create", "ks_server_submit",
            "ks_server_progress", "ks_server_poll", "ks_server_stats", "ks_server_destroy"]
@@ -46,7 +47,8 @@ class Options(C.Structure):
                 ("max_iter", C.c_int), ("diis_space", C.c_int), ("jk_chunks", C.c_int),
                 ("xc_chunks", C.c_int), ("guess", C.c_int), ("xc_points", C.c_int),
                 ("xc_waves", C.c_int), ("direct", C.c_int), ("schwarz_tol", C.c_double),
-                ("basis", C.c_int), ("graphs", C.c_int)]
+                ("basis", C.c_int), ("graphs", C.c_int), ("coarse_rad", C.c_int),
+                ("coarse_theta", C.c_int), ("coarse_phi", C.c_int)]
 
 
 _lib = None
@@ -83,6 +85,8 @@ def load():
     L.ks_kernel_counts.restype = C.c_int
     L.ks_get_convergence.argtypes = [vp, C.c_int, dp, dp, dp]
     L.ks_get_convergence.restype = C.c_int
+    L.ks_get_iterations.argtypes = [vp, C.c_int, ip, ip]
+    L.ks_get_iterations.restype = C.c_int
     L.ks_batch_destroy.argtypes = [vp]
     L.ks_batch_destroy.restype = None
     L.ks_server_create.argtypes = [C.POINTER(Options), C.c_size_t, C.c_int, C.POINTER(vp)]
@@ -222,6 +226,12 @@ class Batch:
         E, dE, err = C.c_double(), C.c_double(), C.c_double()
         _check(load().ks_get_convergence(self.h, m, C.byref(E), C.byref(dE), C.byref(err)))
         return E.value, dE.value, err.value
+
+    def iterations(self, m):
+        """(iterations so far, of which on the coarse start grid)."""
+        n, c = C.c_int(), C.c_int()
+        _check(load().ks_get_iterations(self.h, m, C.byref(n), C.byref(c)))
+        return n.value, c.value
 
     # -- results ----------------------------------------------------------
     def result(self, m):

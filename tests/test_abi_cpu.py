@@ -78,6 +78,13 @@ def test_rejects_bad_options(lib):
     assert st == -1 and "graphs" in err
     st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], basis=2)
     assert st == -1 and "basis" in err
+    # coarse start grid: all three counts or none, each within the main grid
+    st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], coarse_rad=25)
+    assert st == -1 and "coarse grid" in err
+    st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], coarse_rad=60, coarse_theta=8, coarse_phi=16)
+    assert st == -1 and "coarse grid" in err
+    st, h, err = _create(lib, [1, 1], [[0, 0, 0], [0, 0, 0.74]], coarse_rad=25, coarse_theta=8, coarse_phi=-1)
+    assert st == -1 and "coarse grid" in err
     # 6-31G covers H, C, N, O: fluorine is rejected before any device work
     st, h, err = _create(lib, [9, 1], [[0, 0, 0], [0, 0, 0.92]], basis=1)
     assert st == -1 and "6-31G" in err
