@@ -5,7 +5,8 @@ A step is one full pass of the hot path over one batch of synthetic molecules
 workload size, seed 2): batch creation
 (host prep, uploads), one-electron integrals, Loewdin, grid and Becke
 weights, ERIs, and SCF iterations (J/K, XC, Fock, DIIS, eigensolve, density)
-until every molecule has converged, then the results copied to the host.
+until every molecule has converged, then the results (energies, orbital
+energies, gaps, densities) copied to the host.
 
 The headline value is the mixed-precision path (ERIs, J/K and XC in FP32);
 the plain FP64 GPU path runs on the same inputs for the speed ratio and the
@@ -167,9 +168,7 @@ def solve_batch(ks, mols, prec, timing, args):
     if timing:
         b.set_timing(True)
     b.scf_solve()
-    res = [b.result(m) for m in range(b.n_mol)]
-    for m, r in enumerate(res):
-        r["n_coarse"] = b.iterations(m)[1]
+    res = b.results()                  # every molecule's E, eps, HOMO/LUMO, gap, P, status, iterations
     return b, res
 
 

@@ -218,6 +218,16 @@ ks_status ks_get_grid(const ks_batch* b, int mol, double* out);
  * norm of the orthogonalised commutator X^T (FPS - SPF) X. */
 ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, double* err);
 
+/* Results of every molecule of the batch in one call, for callers that
+ * retire whole batches (host buffers; any pointer may be NULL): E, homo,
+ * lumo, gap, status, n_iter and n_coarse [n_mol] as ks_get_result and
+ * ks_get_iterations give them; eps [sum of nbf] with molecule m's orbital
+ * energies after those of molecules 0..m-1; P [sum of nbf^2] with molecule
+ * m's row-major N x N density after those of molecules 0..m-1.  One
+ * device-to-host copy per array. */
+ks_status ks_get_results(const ks_batch* b, double* E, double* homo, double* lumo, double* gap, int* status,
+                         int* n_iter, int* n_coarse, double* eps, double* P);
+
 /* Iterations of molecule mol so far: all of them (*n_iter) and those whose XC
  * ran on the coarse start grid (*n_coarse; 0 without one).  Either pointer
  * may be NULL. */

@@ -1137,6 +1137,35 @@ ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, 
     return KS_OK;
 }
 
+ks_status ks_get_results(const ks_batch* b, double* E, double* homo, double* lumo, double* gap, int* status,
+                         int* n_iter, int* n_coarse, double* eps, double* P)
+{
+    CHECK_B(b);
+    const int n = b->n_mol;
+    long nao = 0;
+    for (const MolDesc& md : b->mol) nao += md.nbf;
+    std::vector<MolState> s(n);
+    std::vector<double> e(nao);
+    KS_HIP(hipMemcpyAsync(s.data(), b->d_state, sizeof(MolState) * n, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipMemcpyAsync(e.data(), b->d_eps, sizeof(double) * nao, hipMemcpyDeviceToHost, b->stream));
+    // the N x N blocks are contiguous in molecule order (mat0 = sum of nbf^2 before)
+    if (P) KS_HIP(hipMemcpyAsync(P, b->d_P, sizeof(double) * b->nmat, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    if (eps) std::memcpy(eps, e.data(), sizeof(double) * nao);
+    for (int m = 0; m < n; m++) {
+        const MolDesc& md = b->mol[m];
+        const double h = e[md.ao0 + md.nocc - 1], l = md.nocc < md.nbf ? e[md.ao0 + md.nocc] : NAN;
+        if (E) E[m] = s[m].E;
+        if (homo) homo[m] = h;
+        if (lumo) lumo[m] = l;
+        if (gap) gap[m] = l - h;
+        if (status) status[m] = s[m].status;
+        if (n_iter) n_iter[m] = s[m].iter;
+        if (n_coarse) n_coarse[m] = s[m].stage ? s[m].iter : s[m].it_full - 1;
+    }
+    return KS_OK;
+}
+
 ks_status ks_get_iterations(const ks_batch* b, int mol, int* n_iter, int* n_coarse)
 {
     CHECK_B(b);

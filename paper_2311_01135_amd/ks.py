@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", 
 EXPORTS = ["ks_default_options", "ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup",
            "eri_build", "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "scf_solve_many",
            "ks_get_result", "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence",
-           "ks_get_iterations", "ks_kernel_times",
+           "ks_get_iterations", "ks_get_results", "ks_kernel_times",
            "ks_kernel_counts", "ks_set_timing",
            "ks_batch_destroy", "ks_last_error", "ks_server_create", "ks_server_submit",
            "ks_server_progress", "ks_server_poll", "ks_server_stats", "ks_server_destroy"]
@@ -87,6 +87,8 @@ def load():
     L.ks_get_convergence.restype = C.c_int
     L.ks_get_iterations.argtypes = [vp, C.c_int, ip, ip]
     L.ks_get_iterations.restype = C.c_int
+    L.ks_get_results.argtypes = [vp, dp, dp, dp, dp, ip, ip, ip, dp, dp]
+    L.ks_get_results.restype = C.c_int
     L.ks_batch_destroy.argtypes = [vp]
     L.ks_batch_destroy.restype = None
     L.ks_server_create.argtypes = [C.POINTER(Options), C.c_size_t, C.c_int, C.POINTER(vp)]
@@ -226,6 +228,29 @@ class Batch:
         E, dE, err = C.c_double(), C.c_double(), C.c_double()
         _check(load().ks_get_convergence(self.h, m, C.byref(E), C.byref(dE), C.byref(err)))
         return E.value, dE.value, err.value
+
+    def results(self, density=True):
+        """Every molecule's result in one call (ks_get_results): a list of
+        dicts with the keys of result() plus n_coarse; eps and P are views
+        into one array each (P omitted with density=False)."""
+        n = self.n_mol
+        E, homo, lumo, gap = (np.zeros(n) for _ in range(4))
+        st, it, nc = (np.zeros(n, dtype=np.int32) for _ in range(3))
+        eps = np.zeros(int(sum(self.nbf)))
+        P = np.zeros(int(sum(N * N for N in self.nbf))) if density else None
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))
+        _check(load().ks_get_results(self.h, _dptr(E), _dptr(homo), _dptr(lumo), _dptr(gap), ip(st), ip(it), ip(nc),
+                                     _dptr(eps), _dptr(P) if density else None))
+        out, a0, m0 = [], 0, 0
+        for m, N in enumerate(self.nbf):
+            r = dict(E=float(E[m]), eps=eps[a0:a0 + N], homo=float(homo[m]), lumo=float(lumo[m]), gap=float(gap[m]),
+                     status=int(st[m]), n_iter=int(it[m]), n_coarse=int(nc[m]))
+            if density:
+                r["P"] = P[m0:m0 + N * N].reshape(N, N)
+            out.append(r)
+            a0 += N
+            m0 += N * N
+        return out
 
     def iterations(self, m):
         """(iterations so far, of which on the coarse start grid)."""

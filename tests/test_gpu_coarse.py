@@ -13,6 +13,8 @@ are those of the main grid.
 - Direct xc_build calls use the main grid whatever the SCF stage.
 - Graph-replayed iterations (the stage switch happens inside the replays)
   equal plain launches.
+- The bulk getter (ks_get_results) returns exactly what the per-molecule
+  getters return.
 """
 import json
 import os
@@ -114,3 +116,17 @@ def test_coarse_start_graph_replay(ks, mols_gold, prec):
             rg, rp = bg.result(m), bp.result(m)
             assert rg["status"] == rp["status"] == 1
             assert abs(rg["E"] - rp["E"]) <= tol and bg.iterations(m)[1] >= 1
+
+
+def test_bulk_results_equal_per_molecule(ks, mols_gold):
+    mols, _ = mols_gold
+    mols = mols[:5] + [molgen.water(0)]
+    with ks.Batch(mols, prec=1, **COARSE) as b:
+        b.scf_solve()
+        bulk = b.results()
+        for m in range(len(mols)):
+            r, q = b.result(m), bulk[m]
+            for k in ("E", "homo", "lumo", "gap", "status", "n_iter"):
+                assert r[k] == q[k], (m, k)
+            assert np.array_equal(r["eps"], q["eps"]) and np.array_equal(r["P"], q["P"])
+            assert b.iterations(m) == (q["n_iter"], q["n_coarse"])
