@@ -77,7 +77,8 @@ static size_t estimate_bytes(const ks_options& o, int natom, int nbf)
     const double es = o.prec == KS_MIXED ? 4.0 : 8.0;
     const double npair = 0.5 * nbf * (nbf + 1.0);
     const double eri = 0.5 * npair * npair * 1.3 * es;
-    const double grid = (double)natom * o.n_rad * o.n_theta * o.n_phi * 32.0;
+    const double grid = (double)natom * ((double)o.n_rad * o.n_theta * o.n_phi
+                                         + (double)o.coarse_rad * o.coarse_theta * o.coarse_phi) * 32.0;
     const double np = std::ceil(nbf / 16.0) * 16.0;
     const double mats = (18.0 + 2.0 * o.diis_space) * nbf * nbf * 8.0;
     const double parts = (2.0 * 8.0 * np * np * 8.0) + 16.0 * np * np * es;

@@ -7,7 +7,8 @@ are those of the main grid.
   against their stored oracle SCF results (tests/golden, written by
   make_golden_subset.py): |dE| <= 1e-8 Ha, |d gap| <= 1e-6 Ha, as without
   the coarse start; and against the same batch without it, max|dP| <= 1e-6.
-- Mixed path, same molecules: |dE|, |d gap| <= 1e-4 Ha against the oracle.
+- Mixed path, same molecules, stored and integral-direct J/K: |dE|,
+  |d gap| <= 1e-4 Ha against the oracle.
 - Iteration accounting: 1 <= coarse iterations <= 12, at least two
   main-grid iterations after them.
 - Direct xc_build calls use the main grid whatever the SCF stage.
@@ -54,12 +55,12 @@ def _solve(ks, mols, **kw):
         return [b.result(m) for m in range(len(mols))], [b.iterations(m) for m in range(len(mols))]
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_coarse_start_matches_oracle(ks, mols_gold, prec):
+@pytest.mark.parametrize("prec,direct", [(0, 0), (1, 0), (1, 1)])
+def test_coarse_start_matches_oracle(ks, mols_gold, prec, direct):
     mols, gold = mols_gold
     tol_e, tol_g = (1e-8, 1e-6) if prec == 0 else (1e-4, 1e-4)
-    print("coarse start, prec %d, %d molecules" % (prec, len(mols)), flush=True)
-    res, its = _solve(ks, mols, prec=prec, **COARSE)
+    print("coarse start, prec %d, direct %d, %d molecules" % (prec, direct, len(mols)), flush=True)
+    res, its = _solve(ks, mols, prec=prec, direct=direct, **COARSE)
     for m, (r, g, (n, nc)) in enumerate(zip(res, gold, its)):
         assert r["status"] == 1, m
         assert abs(r["E"] - g["E"]) <= tol_e, (m, r["E"], g["E"])

@@ -56,11 +56,14 @@ def _serve(ks, mols, budget, **opt):
     return [out[i] for i in range(len(mols))], peak
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_alone_equals_mix(ks, prec):
+@pytest.mark.parametrize("prec,coarse", [(0, False), (1, False), (1, True)])
+def test_alone_equals_mix(ks, prec, coarse):
     mols = _mols()
-    alone = _alone(ks, mols, prec=prec)
-    served, peak = _serve(ks, mols, budget=600 << 20, prec=prec)
+    opt = dict(prec=prec)
+    if coarse:                                  # per-molecule coarse-grid stage
+        opt.update(coarse_rad=25, coarse_theta=8, coarse_phi=16)
+    alone = _alone(ks, mols, **opt)
+    served, peak = _serve(ks, mols, budget=600 << 20, **opt)
     tol = 1e-10 if prec == 0 else 1e-6
     for a, s in zip(alone, served):
         assert s is not None and s["status"] == 1 and a["status"] == 1
