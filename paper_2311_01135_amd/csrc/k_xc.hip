@@ -106,6 +106,81 @@ __global__ __launch_bounds__(64) void grid_kernel(const MolDesc* __restrict__ mo
     o[3] = w;
 }
 
+// Register form for the FP32 cell functions of molecules of at most NA
+// atoms: each thread keeps its distances and cell products in registers
+// (fully unrolled loops, guarded by the molecule's atom count, which is
+// uniform over the work group) and reads the inverse interatomic distances
+// from LDS at the same address on every lane.  The products are formed in
+// the same order as in grid_kernel.
+template <int NA>
+__global__ __launch_bounds__(64) void grid_kernel_reg(const MolDesc* __restrict__ mols, const double* __restrict__ Rat,
+                                                      const double* __restrict__ radial, const double* __restrict__ ang,
+                                                      int nrad, int nth, int nph, int coarse, double* __restrict__ out)
+{
+    const int m = blockIdx.y;
+    const MolDesc md = mols[m];
+    const long base = coarse ? md.gridc0 : md.grid0, ng = coarse ? md.ngridc : md.ngrid;
+    const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double Ra[3 * NA];
+    __shared__ float invR[NA * NA];                  // row stride NA
+    const int na = md.natom;
+    for (int i = threadIdx.x; i < 3 * na; i += blockDim.x) Ra[i] = Rat[3 * md.atom0 + i];
+    for (int i = threadIdx.x; i < na * na; i += blockDim.x) {
+        const int a = i / na, c = i % na;
+        const double* pa = Rat + 3 * (md.atom0 + a);
+        const double* pc = Rat + 3 * (md.atom0 + c);
+        const double dx = pa[0] - pc[0], dy = pa[1] - pc[1], dz = pa[2] - pc[2];
+        invR[a * NA + c] = a == c ? 0.0f : float(1.0 / sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    __syncthreads();
+    if (l >= ng) return;
+    const int per_atom = nrad * nth * nph;
+    const int A = (int)(l / per_atom);
+    int rem = (int)(l % per_atom);
+    const int i = rem / (nth * nph);
+    rem %= nth * nph;
+    const int j = rem / nph, k = rem % nph;
+    const double ct = ang[j], st = sqrt(1.0 - ct * ct), ph = 2.0 * kPi * k / nph;
+    const double r = radial[i];
+    double p[3];
+    p[0] = Ra[3 * A] + r * st * cos(ph);
+    p[1] = Ra[3 * A + 1] + r * st * sin(ph);
+    p[2] = Ra[3 * A + 2] + r * ct;
+    float d[NA], P[NA];
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+        d[a] = 0.0f;
+        P[a] = 1.0f;
+        if (a < na) {
+            const double dx = p[0] - Ra[3 * a], dy = p[1] - Ra[3 * a + 1], dz = p[2] - Ra[3 * a + 2];
+            d[a] = float(sqrt(dx * dx + dy * dy + dz * dz));
+        }
+    }
+    float num = 0.0f, den = 0.0f;
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+        if (a < na) {
+            float Pa = P[a];
+#pragma unroll
+            for (int c = a + 1; c < NA; c++) {
+                if (c < na) {
+                    const float f = becke_f3<float>((d[a] - d[c]) * invR[a * NA + c]);
+                    Pa *= 0.5f * (1.0f - f);
+                    P[c] *= 0.5f * (1.0f + f);
+                }
+            }
+            if (a == A) num = Pa;
+            den += Pa;
+        }
+    }
+    const double w = radial[nrad + i] * ang[nth + j] * (2.0 * kPi / nph) * ((double)num / (double)den);
+    double* o = out + 4 * (base + l);
+    o[0] = p[0];
+    o[1] = p[1];
+    o[2] = p[2];
+    o[3] = w;
+}
+
 template <typename T>
 static ks_status run_grid(ks_batch* b, hipStream_t s, bool coarse)
 {
@@ -119,6 +194,22 @@ static ks_status run_grid(ks_batch* b, hipStream_t s, bool coarse)
     auto lds_for = [&](int n) {
         return sizeof(double) * 3 * maxat + sizeof(T) * ((size_t)maxat * maxat + 2 * (size_t)maxat * n);
     };
+    const ks_options& o = b->opt;
+    if constexpr (sizeof(T) == 4) {
+        if (maxat <= 48) {
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3((unsigned)((maxg + 63) / 64), b->n_mol), dim3(64), 0, s, b->d_mol,
+                                   b->d_R, coarse ? b->d_radial_c : b->d_radial, coarse ? b->d_ang_c : b->d_ang,
+                                   coarse ? o.coarse_rad : o.n_rad, coarse ? o.coarse_theta : o.n_theta,
+                                   coarse ? o.coarse_phi : o.n_phi, (int)coarse, b->d_grid);
+            };
+            if (maxat <= 16) go(grid_kernel_reg<16>);
+            else if (maxat <= 32) go(grid_kernel_reg<32>);
+            else go(grid_kernel_reg<48>);
+            KS_HIP(hipGetLastError());
+            return KS_OK;
+        }
+    }
     while (bs > 16 && lds_for(bs) > 163840) bs /= 2;
     const size_t lds = lds_for(bs);
     if (lds > 163840) {
@@ -126,7 +217,6 @@ static ks_status run_grid(ks_batch* b, hipStream_t s, bool coarse)
         return KS_EUNSUPPORTED;
     }
     KS_HIP(hipFuncSetAttribute((const void*)grid_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const ks_options& o = b->opt;
     hipLaunchKernelGGL(grid_kernel<T>, dim3((unsigned)((maxg + bs - 1) / bs), b->n_mol), dim3(bs), lds, s,
                        b->d_mol, b->d_R, coarse ? b->d_radial_c : b->d_radial, coarse ? b->d_ang_c : b->d_ang,
                        coarse ? o.coarse_rad : o.n_rad, coarse ? o.coarse_theta : o.n_theta,
