@@ -82,11 +82,11 @@ template <> struct BoysOrder<float> { static constexpr int K = 4; };
 // F_0..F_L at T: Taylor expansion about the nearest table node for the top
 // order (dF_m/dT = -F_{m+1}), downward recursion F_m = (2T F_{m+1} + e^-T)/(2m+1);
 // above the table, F_0 = sqrt(pi/T)/2 and upward recursion.
-template <int L, typename R>
+template <int L, typename R, int KT = 0>
 __device__ __forceinline__ void boys(R T, R (&F)[L + 1], const R* __restrict__ tab)
 {
     if (T < R(kBoysTMax)) {
-        constexpr int K = BoysOrder<R>::K;
+        constexpr int K = KT > 0 ? KT : BoysOrder<R>::K;
         int i = (int)(T * R(1.0 / kBoysDT) + R(0.5));
         R dt = R(i) * R(kBoysDT) - T;
         const R* row = tab + (size_t)i * kBoysM + L;
@@ -221,8 +221,8 @@ struct PairView {
 //           sum_tuv E^ab_tuv sum_tau,nu,phi (-1)^(tau+nu+phi) E^cd_tau,nu,phi R_{t+tau,u+nu,v+phi}
 // ---------------------------------------------------------------------------
 // ROWS: tab is the Boys row table of L = LA + LB + LC + LD (boys_rows), else
-// the full table (boys).
-template <int LA, int LB, int LC, int LD, typename R, bool ROWS = false, int PP = kNPrimPair>
+// the full table (boys) with BK Taylor terms (0: the type's default).
+template <int LA, int LB, int LC, int LD, typename R, bool ROWS = false, int PP = kNPrimPair, int BK = 0>
 __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, const Shell& sc, const Shell& sd,
                                             const PairView<PP>& vb, const PairView<PP>& vk, const R* __restrict__ tab,
                                             R cut, R* acc)
@@ -256,7 +256,7 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
             const R T = alpha * (PQx * PQx + PQy * PQy + PQz * PQz);
             R F[L + 1];
             if constexpr (ROWS) boys_rows<L>(T, F, tab);
-            else boys<L, R>(T, F, tab);
+            else boys<L, R, BK>(T, F, tab);
             R Rt[L + 1][L + 1][L + 1];
             hermite_R<L, R>(R(-2) * alpha, PQx, PQy, PQz, F, Rt);
 #pragma unroll
@@ -419,7 +419,11 @@ __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
     const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
     R acc[NCOMP];
     const PairView<PP> vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
-    eri_quartet<LA, LB, LC, LD, R, false, PP>(sa, sb, sc, sd, vb, vk, (const R*)g.tab, R(g.cut), acc);
+    // integrals stored in FP32: five Taylor terms of the Boys function
+    // (truncation below 0.025^5/5! ~ 1e-10 relative, far under the FP32
+    // rounding of the stored value) instead of seven
+    eri_quartet<LA, LB, LC, LD, R, false, PP, sizeof(S) == 4 ? 5 : 0>(sa, sb, sc, sd, vb, vk, (const R*)g.tab,
+                                                                       R(g.cut), acc);
 #pragma unroll
     for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
 }
