@@ -89,7 +89,9 @@ typedef struct {
                                iteration's launches as a captured HIP graph (needs a non-NULL stream at
                                ks_batch_create; ignored while kernel timing is on).  0 = plain launches */
     int coarse_rad, coarse_theta, coarse_phi;
-                            /* optional coarse-grid start (all three > 0 to enable, 0 = off): every
+                            /* optional coarse-grid start (all three > 0 to enable, 0 = off; the paper,
+                               section 3.1, evaluates V_XC on one grid throughout, and this start only
+                               changes the path to the same converged result): every
                                molecule begins its SCF with XC on a coarse_rad x coarse_theta x coarse_phi
                                grid per atom and moves to the main grid once |dE| < 1e-4 Ha and the
                                commutator < 1e-3 there (or after 12 iterations).  DIIS keeps its history
@@ -218,8 +220,10 @@ ks_status ks_get_grid(const ks_batch* b, int mol, double* out);
  * norm of the orthogonalised commutator X^T (FPS - SPF) X. */
 ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, double* err);
 
-/* Results of every molecule of the batch in one call, for callers that
- * retire whole batches (host buffers; any pointer may be NULL): E, homo,
+/* Results of every molecule of the batch in one call (the outputs of paper
+ * section 3.1: energy, orbital energies, density and HOMO-LUMO gap), for
+ * callers that retire whole batches (host buffers; any pointer may be NULL;
+ * KS_EINVAL for a NULL batch, KS_EDEVICE if a copy fails): E, homo,
  * lumo, gap, status, n_iter and n_coarse [n_mol] as ks_get_result and
  * ks_get_iterations give them; eps [sum of nbf] with molecule m's orbital
  * energies after those of molecules 0..m-1; P [sum of nbf^2] with molecule
