@@ -116,6 +116,9 @@ def test_null_handle_calls(lib):
     assert lib.scf_solve_many(None, 1) == -1
     arr = (C.c_void_p * 2)(None, None)
     assert lib.scf_solve_many(arr, 2) == -1
+    assert lib.ks_get_results(None, None, None, None, None, None, None, None, None, None) == -1
+    n, c = C.c_int(), C.c_int()
+    assert lib.ks_get_iterations(None, 0, C.byref(n), C.byref(c)) == -1
     lib.ks_batch_destroy(None)
 
 
