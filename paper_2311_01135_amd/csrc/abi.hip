@@ -1132,7 +1132,7 @@ ks_status ks_get_convergence(const ks_batch* b, int mol, double* E, double* dE, 
     KS_HIP(hipMemcpyAsync(&s, b->d_state + mol, sizeof(MolState), hipMemcpyDeviceToHost, b->stream));
     KS_HIP(hipStreamSynchronize(b->stream));
     if (E) *E = s.E;
-    if (dE) *dE = s.E - s.Eprev;
+    if (dE) *dE = s.dE;
     if (err) *err = s.err;
     return KS_OK;
 }

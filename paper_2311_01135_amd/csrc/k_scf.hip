@@ -360,7 +360,6 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
             nkeep = n;
             st.nhist = n;
             st.head = head;
-            st.Eprev = E;
         }
         __syncthreads();
         const int n = nkeep;
@@ -377,6 +376,8 @@ __global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
     if (threadIdx.x == 0) {
         st.iter = it;
         st.err = err;
+        st.dE = E - st.Eprev;
+        if (!(conv || last)) st.Eprev = E;
         if (to_main && !last) {
             // the next F comes from the main grid; the DIIS history of the
             // coarse-grid iterations stays (restarting it cost 0.4 more

@@ -119,6 +119,7 @@ struct MolState {
     int it_full;            // first iteration on the main grid (convergence is tested after it)
     int pad;
     double E, Eprev, err;
+    double dE;              // E - E of the previous iteration, as last tested
     double Eterms[6];
     double B[kMaxDiis * kMaxDiis];   // DIIS overlaps of the held error vectors
 };

@@ -42,6 +42,7 @@ def test_graph_steps_equal_plain_steps(ks, prec):
             ks.Batch(mols, prec=prec, graphs=0, stream=s2.cuda_stream) as bp:
         scratch = torch.zeros(1 << 20, device="cuda")
         steps = 0
+        prevE = [None] * len(mols)
         while True:
             ng = bg.scf_step()
             # eager work and synchronisations between the replays
@@ -55,6 +56,15 @@ def test_graph_steps_equal_plain_steps(ks, prec):
                 Eg, dEg, eg = bg.convergence(m)
                 Ep, dEp, ep = bp.convergence(m)
                 assert abs(Eg - Ep) <= tol, (steps, m, Eg, Ep)
+                # dE is this iteration's energy minus the previous one's (the
+                # first iteration compares with 0); a retired molecule keeps
+                # the values of its last iteration
+                if prevE[m] is not None and Ep != prevE[m][0]:
+                    assert abs(dEp - (Ep - prevE[m][0])) <= 1e-12 * max(1.0, abs(Ep)), (steps, m, dEp, Ep, prevE[m])
+                    assert abs(dEg - (Eg - prevE[m][1])) <= 1e-12 * max(1.0, abs(Eg)), (steps, m, dEg, Eg, prevE[m])
+                elif prevE[m] is None:
+                    assert dEp == Ep and dEg == Eg, (steps, m, dEp, Ep)
+                prevE[m] = (Ep, Eg)
                 assert abs(eg - ep) <= tol, (steps, m, eg, ep)
                 assert np.abs(bg.matrix(m, "P") - bp.matrix(m, "P")).max() <= tol, (steps, m)
             if ng == 0:
