@@ -202,12 +202,31 @@ def coarse_options(args):
 
 def serve_run(ks, reqs, arrivals, prec, **options):
     """Drive a ks.Server with requests arriving at the given times (s); returns
-    (wall seconds, latencies from scheduled arrival to observed completion)."""
+    (wall seconds, latencies from scheduled arrival to observed completion,
+    NaN for a rejected request, number rejected, iterations per request)."""
     srv = ks.Server(prec=prec, **options)
     n = len(reqs)
-    lat = np.zeros(n)
+    lat = np.full(n, np.nan)
+    iters = np.zeros(n, dtype=np.int64)
     pending = {}
-    nxt, done = 0, 0
+    nxt, done, rejected = 0, 0, 0
+
+    def collect(now):
+        nonlocal done, rejected
+        for tk in list(pending):
+            try:
+                r = srv.poll(tk)
+            except ks.KsError:              # rejected at admission: done, with an error
+                pending.pop(tk)
+                done += 1
+                rejected += 1
+                continue
+            if r is not None:
+                i = pending.pop(tk)
+                lat[i] = now - arrivals[i]
+                iters[i] = r["n_iter"]
+                done += 1
+
     t0 = time.perf_counter()
     while done < n:
         t = time.perf_counter() - t0
@@ -217,20 +236,17 @@ def serve_run(ks, reqs, arrivals, prec, **options):
             nxt += 1
         st = srv.stats()
         if st["queued"] == 0 and st["resident"] == 0:
-            if nxt < n:
+            collect(time.perf_counter() - t0)   # requests rejected while nothing was resident
+            if done < n and nxt < n:
                 time.sleep(max(0.0, min(0.01, arrivals[nxt] - (time.perf_counter() - t0))))
+            elif done < n and not pending:
+                raise RuntimeError("serving: %d requests neither finished nor pending" % (n - done))
             continue
         if srv.progress() > 0:
-            now = time.perf_counter() - t0
-            for tk in list(pending):
-                r = srv.poll(tk)
-                if r is not None:
-                    i = pending.pop(tk)
-                    lat[i] = now - arrivals[i]
-                    done += 1
+            collect(time.perf_counter() - t0)
     wall = time.perf_counter() - t0
     srv.close()
-    return wall, lat
+    return wall, lat, rejected, iters
 
 
 def serving_leg(ks, args):
@@ -239,15 +255,17 @@ def serving_leg(ks, args):
     from paper_2311_01135_amd import molgen
     n = args.serve_requests
     reqs = molgen.batch(n, 3, (3, 11))
-    wall_sat, _ = serve_run(ks, reqs, np.zeros(n), ks.KS_MIXED, **coarse_options(args))
-    sat = n / wall_sat
+    wall_sat, _, rej_sat, _ = serve_run(ks, reqs, np.zeros(n), ks.KS_MIXED, **coarse_options(args))
+    sat = (n - rej_sat) / wall_sat
     lam = 0.8 * sat
     rng = np.random.default_rng(3)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
-    wall, lat = serve_run(ks, reqs, arrivals, ks.KS_MIXED, **coarse_options(args))
+    wall, lat, rej, iters = serve_run(ks, reqs, arrivals, ks.KS_MIXED, **coarse_options(args))
+    ok = lat[np.isfinite(lat)]
     return dict(requests=n, heavy_atoms="3-11", precision="mixed", saturated_solves_per_s=sat,
-                arrival_rate_per_s=lam, solves_per_s=n / wall, p50_latency_s=float(np.percentile(lat, 50)),
-                p99_latency_s=float(np.percentile(lat, 99)), max_latency_s=float(lat.max()))
+                arrival_rate_per_s=lam, solves_per_s=len(ok) / wall, p50_latency_s=float(np.percentile(ok, 50)),
+                p99_latency_s=float(np.percentile(ok, 99)), max_latency_s=float(ok.max()),
+                rejected=int(rej + rej_sat), mean_iterations=float(iters[np.isfinite(lat)].mean()))
 
 
 def cpu_baseline(mols, args):

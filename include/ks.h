@@ -279,7 +279,13 @@ ks_status ks_server_submit(ks_server* s, int n_atoms, const int* Z, const double
  * resident batch on its own stream), admission of queued requests while the
  * budget allows (their integrals and grid are built while the iterations
  * run), then retirement of converged molecules and release of empty batches.
- * *n_finished = requests completed in this call. */
+ * *n_finished = requests completed in this call.  The budget check uses an
+ * estimate of each request's device bytes; when a batch creation still runs
+ * out of device memory its requests stay queued until a resident batch is
+ * released (with nothing resident the wave is retried with one request, and
+ * a single request that does not fit is rejected: ks_server_poll then
+ * returns KS_ENOMEM for it).  Other admission failures reject the wave and
+ * are returned. */
 ks_status ks_server_progress(ks_server* s, int* n_finished);
 
 /* Result of a ticket: KS_OK when finished (outputs filled; latency_s from
@@ -291,6 +297,12 @@ ks_status ks_server_poll(const ks_server* s, long ticket, double* E, double* hom
 /* Queue length, resident (still iterating) molecules, completed requests and
  * device bytes held by resident batches. */
 ks_status ks_server_stats(const ks_server* s, int* queued, int* resident, long* done, size_t* bytes_in_use);
+
+/* Testing hook for the admission error path: the next n admission attempts
+ * of this server fail with KS_ENOMEM before touching the device, as if the
+ * batch creation had run out of device memory.  KS_EINVAL for a NULL handle
+ * or n < 0. */
+ks_status ks_server_fail_admissions(ks_server* s, int n);
 
 /* Releases every resident batch.  NULL-safe. */
 void ks_server_destroy(ks_server* s);

@@ -63,6 +63,8 @@ struct ks_server {
     std::vector<Result> results;
     size_t in_use = 0;
     long n_done = 0;
+    bool wait_retire = false;   // an admission ran out of device memory: retry once a batch is released
+    int fail_admissions = 0;    // testing hook: admissions that fail as if out of device memory
     clk::time_point t0;
 };
 
@@ -130,16 +132,23 @@ static void drop_resident(ks_server* s, size_t i)
     if (r.stream) (void)hipStreamDestroy(r.stream);
     s->in_use -= std::min(s->in_use, r.bytes);
     s->res.erase(s->res.begin() + i);
+    s->wait_retire = false;
 }
 
-// Admit queued requests into one new batch while the budget allows.
-static ks_status admit(ks_server* s)
+// Admit queued requests (at most cap) into one new batch while the budget
+// allows.  The byte count per request is an estimate, so batch creation can
+// still run out of device memory: then the requests stay queued and
+// admission waits until a resident batch is released; with nothing resident
+// the wave is retried with its first request alone, and only a single
+// request that does not fit an empty device is rejected.
+static ks_status admit(ks_server* s, int cap)
 {
     if (s->queue.empty()) return KS_OK;
+    if (s->wait_retire && !s->res.empty()) return KS_OK;
     size_t add = 0;
     int n = 0;
     for (const Request& q : s->queue) {
-        if (n >= s->max_batch) break;
+        if (n >= s->max_batch || n >= cap) break;
         if (s->in_use + add + q.est_bytes > s->budget && !(s->res.empty() && n == 0)) break;
         add += q.est_bytes;
         n++;
@@ -158,12 +167,34 @@ static ks_status admit(ks_server* s)
         r.tickets.push_back(q.ticket);
     }
     KS_HIP(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
-    ks_status st = ks_batch_create(&s->opt, n, na.data(), Z.data(), xyz.data(), ch.data(), r.stream, &r.b);
-    if (st == KS_OK) st = ks_setup(r.b);
-    if (st == KS_OK) st = eri_build(r.b);
+    ks_status st;
+    if (s->fail_admissions > 0) {
+        s->fail_admissions--;
+        set_error("admission failed: device memory (injected)");
+        st = KS_ENOMEM;
+    } else {
+        st = ks_batch_create(&s->opt, n, na.data(), Z.data(), xyz.data(), ch.data(), r.stream, &r.b);
+        if (st == KS_OK) st = ks_setup(r.b);
+        if (st == KS_OK) st = eri_build(r.b);
+    }
     if (st != KS_OK) {
-        // the whole admission wave is rejected (each request was validated at
-        // submit; this is a device or overlap failure)
+        if (r.b) ks_batch_destroy(r.b);
+        (void)hipStreamDestroy(r.stream);
+        if (st == KS_ENOMEM) {
+            if (!s->res.empty()) {
+                s->wait_retire = true;        // the wave stays queued
+                return KS_OK;
+            }
+            if (n > 1) return admit(s, 1);
+            Result& o = s->results[s->queue.front().ticket];
+            o.state = 3;
+            o.err = st;
+            o.t_done = now_s(s);
+            s->queue.pop_front();
+            return KS_OK;
+        }
+        // each request was validated at submit: this is a device failure,
+        // and the whole admission wave is rejected
         for (int i = 0; i < n; i++) {
             Result& o = s->results[s->queue.front().ticket];
             o.state = 3;
@@ -171,9 +202,7 @@ static ks_status admit(ks_server* s)
             o.t_done = now_s(s);
             s->queue.pop_front();
         }
-        if (r.b) ks_batch_destroy(r.b);
-        (void)hipStreamDestroy(r.stream);
-        return st == KS_ENOMEM ? KS_OK : st;
+        return st;
     }
     for (int i = 0; i < n; i++) {
         s->results[s->queue.front().ticket].state = 1;
@@ -268,7 +297,7 @@ ks_status ks_server_progress(ks_server* s, int* n_finished)
         }
     }
     // 2. admit newcomers while those iterations run
-    if ((st = admit(s))) return st;
+    if ((st = admit(s, s->max_batch))) return st;
     // 3. wait, retire converged molecules, release empty batches
     for (Resident& r : s->res) {
         if (!r.launched) continue;
@@ -316,6 +345,16 @@ ks_status ks_server_stats(const ks_server* s, int* queued, int* resident, long* 
     if (resident) *resident = nres;
     if (done) *done = s->n_done;
     if (bytes_in_use) *bytes_in_use = s->in_use;
+    return KS_OK;
+}
+
+ks_status ks_server_fail_admissions(ks_server* s, int n)
+{
+    if (!s || n < 0) {
+        set_error("server handle is NULL or count negative");
+        return KS_EINVAL;
+    }
+    s->fail_admissions = n;
     return KS_OK;
 }
 

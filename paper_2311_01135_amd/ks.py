@@ -32,7 +32,8 @@ EXPORTS = ["ks_default_options", "ks_batch_create", "ks_batch_sizes", "ks_batch_
            "ks_get_iterations", "ks_get_results", "ks_kernel_times",
            "ks_kernel_counts", "ks_set_timing",
            "ks_batch_destroy", "ks_last_error", "ks_server_create", "ks_server_submit",
-           "ks_server_progress", "ks_server_poll", "ks_server_stats", "ks_server_destroy"]
+           "ks_server_progress", "ks_server_poll", "ks_server_stats", "ks_server_fail_admissions",
+           "ks_server_destroy"]
 
 
 class KsError(RuntimeError):
@@ -96,9 +97,11 @@ def load():
     L.ks_server_progress.argtypes = [vp, ip]
     L.ks_server_poll.argtypes = [vp, C.c_long, dp, dp, dp, dp, ip, ip, dp]
     L.ks_server_stats.argtypes = [vp, ip, ip, lp, C.POINTER(C.c_size_t)]
+    L.ks_server_fail_admissions.argtypes = [vp, C.c_int]
     L.ks_server_destroy.argtypes = [vp]
     L.ks_server_destroy.restype = None
-    for name in ("ks_server_create", "ks_server_submit", "ks_server_progress", "ks_server_poll", "ks_server_stats"):
+    for name in ("ks_server_create", "ks_server_submit", "ks_server_progress", "ks_server_poll", "ks_server_stats",
+                 "ks_server_fail_admissions"):
         getattr(L, name).restype = C.c_int
     L.ks_last_error.restype = C.c_char_p
     for name in ("ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup", "eri_build",
@@ -348,6 +351,10 @@ class Server:
         _check(rc)
         return dict(E=E.value, homo=homo.value, lumo=lumo.value, gap=gap.value, status=st.value,
                     n_iter=it.value, latency=lat.value)
+
+    def fail_admissions(self, n: int):
+        """Testing hook: the next n admissions fail as if out of device memory."""
+        _check(load().ks_server_fail_admissions(self.h, n))
 
     def stats(self):
         q, r, d, by = C.c_int(), C.c_int(), C.c_long(), C.c_size_t()

@@ -108,3 +108,49 @@ def test_solve_many_equals_separate(ks, prec):
     finally:
         for b in bs:
             b.close()
+
+
+def test_admission_out_of_memory_requeues(ks):
+    """An admission that runs out of device memory (injected on the host)
+    leaves its requests queued while a batch is resident, retries a lone
+    request when nothing is resident, and rejects only a single request that
+    fails on an empty device; every other request completes with the result
+    it has alone."""
+    mols = _mols()[:5]
+    alone = _alone(ks, mols)
+    with ks.Server(max_batch=2) as s:
+        t = [s.submit(z, x) for z, x in mols[:2]]
+        s.progress()                            # first wave resident
+        assert s.stats()["resident"] == 2
+        t += [s.submit(z, x) for z, x in mols[2:4]]
+        s.fail_admissions(1)
+        s.progress()                            # fails with a batch resident: stays queued
+        st = s.stats()
+        assert st["queued"] == 2, st
+        for tk in t[2:]:
+            assert s.poll(tk) is None
+        for _ in range(200):
+            s.progress()
+            if s.stats()["done"] == 4:
+                break
+        got = [s.poll(tk) for tk in t]
+        assert s.stats()["queued"] == 0 and s.stats()["bytes"] == 0
+        for a, r in zip(alone[:4], got):
+            assert r is not None and r["status"] == 1
+            assert abs(a["E"] - r["E"]) <= 1e-10 and abs(a["gap"] - r["gap"]) <= 1e-10
+        # nothing resident: the wave of two fails, the lone retry fails, so
+        # the first request is rejected and the second admitted next round
+        t2 = [s.submit(z, x) for z, x in (mols[4], mols[0])]
+        s.fail_admissions(2)
+        s.progress()
+        with pytest.raises(ks.KsError) as e:
+            s.poll(t2[0])
+        assert e.value.status == -2
+        for _ in range(200):
+            s.progress()
+            if s.stats()["done"] == 5:
+                break
+        r = s.poll(t2[1])
+        assert r is not None and abs(r["E"] - alone[0]["E"]) <= 1e-10
+        with pytest.raises(ks.KsError):
+            s.fail_admissions(-1)
