@@ -5,8 +5,15 @@ are those of the main grid.
 
 - FP64: the first 8 molecules of the 9-11-heavy-atom benchmark set (seed 2)
   against their stored oracle SCF results (tests/golden, written by
-  make_golden_subset.py): |dE| <= 1e-8 Ha, |d gap| <= 1e-6 Ha, as without
-  the coarse start; and against the same batch without it, max|dP| <= 1e-6.
+  make_golden_subset.py): |dE| <= 1e-8 Ha and max|dP| <= 1e-6 (molecules
+  0-2, make_golden_density.py).  The gap is held to 1e-6 Ha here, not the
+  1e-8 of a run without the coarse start: with it the iterates differ from
+  the oracle's, so the two runs stop at different points inside the
+  stopping rule (commutator max-norm < 1e-7), and orbital energies, unlike
+  the energy, move to first order with that residual.  The fixed point
+  itself is the oracle's: converged tightly (dE < 1e-12 Ha, commutator
+  < 1e-10) on both sides, E and the gap agree to 1e-8 Ha and P to 1e-6.
+  Against the same batch without the coarse start, max|dP| <= 1e-6.
 - Mixed path, same molecules, stored and integral-direct J/K: |dE|,
   |d gap| <= 1e-4 Ha against the oracle.
 - Iteration accounting: 1 <= coarse iterations <= 12, at least two
@@ -29,6 +36,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_scf_seed2_first64.json")
+DENS = os.path.join(os.path.dirname(__file__), "golden", "oracle_density_seed2")
 COARSE = dict(coarse_rad=25, coarse_theta=8, coarse_phi=16)
 NMOL = 8
 
@@ -68,11 +76,36 @@ def test_coarse_start_matches_oracle(ks, mols_gold, prec, direct):
         assert 1 <= nc <= 12 and n >= nc + 2, (m, n, nc)
         assert r["n_iter"] == n
     if prec == 0:
+        dens = np.load(DENS + ".npz")
+        for m in range(3):
+            dP = np.abs(res[m]["P"] - dens["P_default_%d" % m]).max()
+            print("molecule %d: max|dP| vs oracle %.2e" % (m, dP), flush=True)
+            assert dP <= 1e-6, (m, dP)
         ref, its0 = _solve(ks, mols, prec=prec)
         for m in range(len(mols)):
             assert its0[m][1] == 0
             assert np.abs(res[m]["P"] - ref[m]["P"]).max() <= 1e-6, m
             assert abs(res[m]["E"] - ref[m]["E"]) <= 1e-8, m
+
+
+def test_coarse_start_tight_fixed_point(ks, mols_gold):
+    """Both sides converged to dE < 1e-12 Ha and commutator < 1e-10: the
+    coarse-start FP64 path reaches the oracle's fixed point (E and gap to
+    1e-8 Ha, P to 1e-6)."""
+    mols, _ = mols_gold
+    with open(DENS + ".json") as f:
+        tight = {t["index"]: t for t in json.load(f)["tight"]}
+    dens = np.load(DENS + ".npz")
+    res, its = _solve(ks, mols, prec=0, e_tol=1e-12, comm_tol=1e-10, max_iter=200, **COARSE)
+    for m, r in enumerate(res):
+        g = tight[m]
+        assert r["status"] == 1 and g["status"] == 1, m
+        print("molecule %d: tight |dE| %.2e |dgap| %.2e, %d iterations (%d coarse), oracle %d"
+              % (m, abs(r["E"] - g["E"]), abs(r["gap"] - g["gap"]), its[m][0], its[m][1], g["n_iter"]), flush=True)
+        assert abs(r["E"] - g["E"]) <= 1e-8, (m, r["E"], g["E"])
+        assert abs(r["gap"] - g["gap"]) <= 1e-8, (m, r["gap"], g["gap"])
+        if m < 3:
+            assert np.abs(r["P"] - dens["P_tight_%d" % m]).max() <= 1e-6, m
 
 
 def test_xc_build_uses_main_grid(ks, mols_gold):
