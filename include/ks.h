@@ -208,6 +208,22 @@ ks_status ks_get_result(const ks_batch* b, int mol, double* E, double* eps, doub
  * ij(ij+1)/2 + kl with ij = i(i+1)/2 + j, i >= j, k >= l, ij >= kl. */
 ks_status ks_get_eri(const ks_batch* b, int mol, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): ks_get_eri
+ * without its temporary device buffer.  Copies the packed ERIs lo ..
+ * lo + count - 1 of molecule mol (FP64, the order of ks_get_eri) to the host
+ * buffer out[count], staged through a library-owned device array of
+ * KS_ERI_WINDOW_MAX doubles (8 MiB, held by each device the library runs on
+ * until the process ends); the whole list is read in windows.  Allocates
+ * nothing.  Errors: KS_EINVAL for a bad molecule, NULL out, count < 0,
+ * count > KS_ERI_WINDOW_MAX or a window outside [0, n_eri); KS_ESTATE before
+ * eri_build or for an integral-direct batch; KS_EDEVICE if the array's
+ * device address cannot be found.  Every call on one device shares that
+ * array, so calls that overlap on one device (other host threads, other
+ * batches' streams) race; calls from one thread in turn are safe. */
+#define KS_ERI_WINDOW_MAX 1048576
+ks_status ks_get_eri_window(const ks_batch* b, int mol, long lo, long count, double* out);
+
 /* Copies a resident N x N matrix of molecule mol to the host:
  * which = 0 S, 1 T, 2 V(nuclear), 3 X = S^-1/2, 4 F, 5 P, 6 J, 7 K, 8 V_xc. */
 ks_status ks_get_matrix(const ks_batch* b, int mol, int which, double* out);

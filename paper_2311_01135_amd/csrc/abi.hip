@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "kernels.h"
@@ -1051,6 +1052,75 @@ ks_status ks_get_eri(const ks_batch* b, int mol, double* out)
     }
     (void)hipFree(d);
     return st;
+}
+
+// Staging array of ks_get_eri_window (callers that cannot allocate device
+// memory): a file-scope device array, so each device holds one copy for the
+// life of the process.  In host code its name is not a device address: the
+// address is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that address is passed to kernels and copies.
+static __device__ __align__(256) double scratch[KS_ERI_WINDOW_MAX];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+static ks_status scratch_address(double** out)
+{
+    int dev = -1;
+    KS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d out of range for the staging array", dev);
+        return KS_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error("hipGetSymbolAddress of the staging array failed: %s", hipGetErrorString(e));
+            return KS_EDEVICE;
+        }
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KS_OK;
+}
+
+ks_status ks_get_eri_window(const ks_batch* b, int mol, long lo, long count, double* out)
+{
+    CHECK_B(b);
+    if (mol < 0 || mol >= b->n_mol || (!out && count > 0)) {
+        set_error("bad molecule index or NULL output");
+        return KS_EINVAL;
+    }
+    if (!b->eri_done) {
+        set_error("ks_get_eri_window before eri_build");
+        return KS_ESTATE;
+    }
+    if (b->opt.direct) {
+        set_error("ks_get_eri_window: an integral-direct batch stores no integrals");
+        return KS_ESTATE;
+    }
+    if (count < 0 || count > KS_ERI_WINDOW_MAX) {
+        set_error("window of %ld integrals: at most %d per call", count, (int)KS_ERI_WINDOW_MAX);
+        return KS_EINVAL;
+    }
+    long neri;
+    ks_batch_sizes(b, mol, nullptr, nullptr, &neri, nullptr);
+    if (lo < 0 || lo + count > neri) {
+        set_error("window %ld .. %ld outside the %ld packed integrals of molecule %d", lo, lo + count, neri, mol);
+        return KS_EINVAL;
+    }
+    if (count == 0) return KS_OK;
+    double* d = nullptr;
+    ks_status st = scratch_address(&d);
+    if (st) return st;
+    if ((st = launch_eri_unpack_window(b, mol, lo, lo + count, d))) return st;
+    KS_HIP(hipMemcpyAsync(out, d, sizeof(double) * count, hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipStreamSynchronize(b->stream));
+    return KS_OK;
 }
 
 ks_status ks_get_matrix(const ks_batch* b, int mol, int which, double* out)

@@ -579,6 +579,36 @@ __global__ void eri_unpack_kernel(const MolDesc* __restrict__ mols, int m, int c
                 }
 }
 
+// The same copy-out restricted to the packed indices lo .. hi-1, written to
+// out[index - lo]: a window of the packed list in a caller-sized buffer.
+// Every index of the window is written (each packed index is the image of at
+// least one component of one unique quartet).
+template <typename S>
+__global__ void eri_unpack_window_kernel(const MolDesc* __restrict__ mols, int m, int c, long nqc,
+                                         const Shell* __restrict__ shells, const Pair* __restrict__ pb,
+                                         const Pair* __restrict__ pk, const S* __restrict__ eri, long lo, long hi,
+                                         double* __restrict__ out)
+{
+    const MolDesc md = mols[m];
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= md.nq[c]) return;
+    int i, j;
+    decode_quartet(c, q, md.npair[class_ket(c)], i, j);
+    const Pair P1 = pb[md.pair0[class_bra(c)] + i], P2 = pk[md.pair0[class_ket(c)] + j];
+    const Shell &A = shells[P1.sa], &B = shells[P1.sb], &Cc = shells[P2.sa], &D = shells[P2.sb];
+    const int na = A.L ? 3 : 1, nb = B.L ? 3 : 1, nc = Cc.L ? 3 : 1, nd = D.L ? 3 : 1;
+    const long qg = md.q0[c] + q;
+    int k = 0;
+    for (int ia = 0; ia < na; ia++)
+        for (int jb = 0; jb < nb; jb++)
+            for (int kc = 0; kc < nc; kc++)
+                for (int ld = 0; ld < nd; ld++, k++) {
+                    const long ij = pidx(A.ao + ia, B.ao + jb), kl = pidx(Cc.ao + kc, D.ao + ld);
+                    const long x = ij >= kl ? ij * (ij + 1) / 2 + kl : kl * (kl + 1) / 2 + ij;
+                    if (x >= lo && x < hi) out[x - lo] = (double)eri[(size_t)k * nqc + qg];
+                }
+}
+
 // ---------------------------------------------------------------------------
 // Schwarz factors: Q_ab = max over the components (a_i b_j) of
 // sqrt|(a_i b_j | a_i b_j)|, so |(ab|cd)| <= Q_ab Q_cd for every component.
@@ -989,6 +1019,25 @@ ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out)
             hipLaunchKernelGGL(eri_unpack_kernel<double>, dim3(nb), dim3(128), 0, b->stream, b->d_mol, mol, c, b->nq[c],
                                b->d_shells, b->d_pairs[class_bra(c)], b->d_pairs[class_ket(c)],
                                (const double*)b->d_eri[c], d_out);
+        KS_HIP(hipGetLastError());
+    }
+    return KS_OK;
+}
+
+ks_status launch_eri_unpack_window(const ks_batch* b, int mol, long lo, long hi, double* d_out)
+{
+    const MolDesc& md = b->mol[mol];
+    for (int c = 0; c < kNClass; c++) {
+        if (!md.nq[c]) continue;
+        const unsigned nb = (unsigned)((md.nq[c] + 127) / 128);
+        if (b->opt.prec == KS_MIXED)
+            hipLaunchKernelGGL(eri_unpack_window_kernel<float>, dim3(nb), dim3(128), 0, b->stream, b->d_mol, mol, c,
+                               b->nq[c], b->d_shells, b->d_pairs[class_bra(c)], b->d_pairs[class_ket(c)],
+                               (const float*)b->d_eri[c], lo, hi, d_out);
+        else
+            hipLaunchKernelGGL(eri_unpack_window_kernel<double>, dim3(nb), dim3(128), 0, b->stream, b->d_mol, mol, c,
+                               b->nq[c], b->d_shells, b->d_pairs[class_bra(c)], b->d_pairs[class_ket(c)],
+                               (const double*)b->d_eri[c], lo, hi, d_out);
         KS_HIP(hipGetLastError());
     }
     return KS_OK;

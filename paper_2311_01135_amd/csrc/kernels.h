@@ -38,6 +38,7 @@ ks_status launch_int1e(ks_batch* b);
 ks_status launch_pairs(ks_batch* b);
 ks_status launch_eri(ks_batch* b);
 ks_status launch_eri_unpack(const ks_batch* b, int mol, double* d_out);
+ks_status launch_eri_unpack_window(const ks_batch* b, int mol, long lo, long hi, double* d_out);
 // Schwarz factors Q_ab = max_component sqrt|(ab|ab)| of every shell pair.
 ks_status launch_schwarz(ks_batch* b);
 ks_status sort_pairs_by_schwarz(ks_batch* b);

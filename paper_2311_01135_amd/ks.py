@@ -21,6 +21,7 @@ KS_XC_HF, KS_XC_B3LYP, KS_XC_B3LYP5 = 0, 1, 2
 KS_FP64, KS_MIXED = 0, 1
 KS_GUESS_ATOM, KS_GUESS_CORE = 0, 1
 KS_BASIS_STO3G, KS_BASIS_631G = 0, 1
+ERI_WINDOW_MAX = 1048576          # KS_ERI_WINDOW_MAX of ks.h
 MOL_ACTIVE, MOL_CONVERGED, MOL_MAXITER, MOL_DIVERGED = 0, 1, 2, 3
 MATRIX = {"S": 0, "T": 1, "V": 2, "X": 3, "F": 4, "P": 5, "J": 6, "K": 7, "Vxc": 8}
 STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", -4: "KS_ENOCONV",
@@ -28,7 +29,7 @@ STATUS_NAMES = {0: "KS_OK", -1: "KS_EINVAL", -2: "KS_ENOMEM", -3: "KS_EDEVICE", 
 
 EXPORTS = ["ks_default_options", "ks_batch_create", "ks_batch_sizes", "ks_batch_quartets", "ks_setup",
            "eri_build", "jk_build", "xc_build", "fock_build", "scf_step", "scf_solve", "scf_solve_many",
-           "ks_get_result", "ks_get_eri", "ks_get_matrix", "ks_get_grid", "ks_get_convergence",
+           "ks_get_result", "ks_get_eri", "ks_get_eri_window", "ks_get_matrix", "ks_get_grid", "ks_get_convergence",
            "ks_get_iterations", "ks_get_results", "ks_kernel_times",
            "ks_kernel_counts", "ks_set_timing",
            "ks_batch_destroy", "ks_last_error", "ks_server_create", "ks_server_submit",
@@ -77,6 +78,8 @@ def load():
     L.scf_solve_many.argtypes = [C.POINTER(vp), C.c_int]
     L.ks_get_result.argtypes = [vp, C.c_int, dp, dp, dp, dp, dp, dp, ip, ip]
     L.ks_get_eri.argtypes = [vp, C.c_int, dp]
+    L.ks_get_eri_window.argtypes = [vp, C.c_int, C.c_long, C.c_long, dp]
+    L.ks_get_eri_window.restype = C.c_int
     L.ks_get_matrix.argtypes = [vp, C.c_int, C.c_int, dp]
     L.ks_get_grid.argtypes = [vp, C.c_int, dp]
     L.ks_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), dp, C.c_int]
@@ -275,6 +278,14 @@ class Batch:
     def eri(self, m):
         out = np.zeros(self.n_eri[m])
         _check(load().ks_get_eri(self.h, m, _dptr(out)))
+        return out
+
+    def eri_window(self, m, lo, count, out=None):
+        """Packed ERIs lo .. lo+count-1 of molecule m (ks_get_eri_window: no
+        device allocation, at most ERI_WINDOW_MAX per call)."""
+        if out is None:
+            out = np.zeros(max(0, count))
+        _check(load().ks_get_eri_window(self.h, m, lo, count, _dptr(out) if count > 0 else None))
         return out
 
     def matrix(self, m, which):
