@@ -20,8 +20,8 @@ __device__ __forceinline__ void lds_add(A* p, A v)
 // I: the quartet's NA NB NC ND components (a slowest); oa..od: first AO of
 // each shell; bra_key: identifies the bra pair (lanes of a wavefront that
 // all share it sum their J_ab contributions before a single LDS atomic).
-template <int NA, int NB, int NC, int ND, typename A>
-__device__ __forceinline__ void jk_scatter(const A (&I)[NA * NB * NC * ND], int oa, int ob, int oc, int od, A f,
+template <int NA, int NB, int NC, int ND, typename A, typename SI = A>
+__device__ __forceinline__ void jk_scatter(const SI (&I)[NA * NB * NC * ND], int oa, int ob, int oc, int od, A f,
                                            int bra_key, int N, const A* __restrict__ Ps, A* AJ, A* AK)
 {
     const int i = bra_key;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void jk_scatter(const A (&I)[NA * NB * NC * ND], int 
             for (int c = 0; c < NC; c++)
 #pragma unroll
                 for (int d = 0; d < ND; d++) {
-                    const A v = I[((a * NB + b) * NC + c) * ND + d];
+                    const A v = A(I[((a * NB + b) * NC + c) * ND + d]);
                     jab[a][b] += v * pcd[c][d];
                     jcd[c][d] += v * pab[a][b];
                     kac[a][c] += v * pbd[b][d];

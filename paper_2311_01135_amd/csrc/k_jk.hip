@@ -74,7 +74,18 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
     const int nket = md.npair[class_ket(C)];
     const int step = blockDim.x;
     int i = 0, j = 0;
-    if (lo + threadIdx.x < hi) decode_quartet_jk(C, lo + threadIdx.x, nket, i, j);
+    // the integrals of the thread's next quartet are loaded one iteration
+    // ahead (classes of up to 27 components), so their HBM latency overlaps
+    // the current quartet's scatter; they stay in the storage type until use
+    constexpr bool kAhead = NCOMP <= 27;
+    S cur[NCOMP];
+    if (lo + threadIdx.x < hi) {
+        decode_quartet_jk(C, lo + threadIdx.x, nket, i, j);
+        if constexpr (kAhead) {
+#pragma unroll
+            for (int k = 0; k < NCOMP; k++) cur[k] = eri[(size_t)k * NQ + md.q0[C] + lo + threadIdx.x];
+        }
+    }
     for (long q = lo + threadIdx.x; q < hi; q += step) {
         const int2 P1 = pb[i], P2 = pk[j];
         const int oa = P1.x & 0xffff, ob = P1.y, oc = P2.x & 0xffff, od = P2.y;
@@ -90,11 +101,20 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
         } else {
             while (j2 >= nket) { j2 -= nket; i2++; }
         }
-        const long qg = md.q0[C] + q;
-        A I[NCOMP];
+        S I[NCOMP];
+        if constexpr (kAhead) {
 #pragma unroll
-        for (int k = 0; k < NCOMP; k++) I[k] = A(eri[(size_t)k * NQ + qg]);
-        jk_scatter<NA, NB, NC, ND, A>(I, oa, ob, oc, od, f, i, N, Ps, AJ, AK);
+            for (int k = 0; k < NCOMP; k++) I[k] = cur[k];
+            if (q + step < hi) {
+                const long qn = md.q0[C] + q + step;
+#pragma unroll
+                for (int k = 0; k < NCOMP; k++) cur[k] = eri[(size_t)k * NQ + qn];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NCOMP; k++) I[k] = eri[(size_t)k * NQ + md.q0[C] + q];
+        }
+        jk_scatter<NA, NB, NC, ND, A, S>(I, oa, ob, oc, od, f, i, N, Ps, AJ, AK);
         i = i2;
         j = j2;
     }
@@ -182,66 +202,79 @@ __device__ __forceinline__ void digest_class_rows(const JkArgs& g, const MolDesc
 
 // GLOBAL (molecules whose 3 N^2 accumulators exceed the LDS): the density
 // is read from dP and the partials of this item are in global memory
-// (A = double), digested bra by bra (digest_class_rows).
+// (A = double), digested bra by bra (digest_class_rows).  Molecules whose
+// accumulators fit the LDS use jk_class_kernel below.
 template <typename S, typename A, bool GLOBAL>
 __global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
+{
+    static_assert(GLOBAL, "LDS-resident digestion runs in jk_class_kernel");
+    static_assert(std::is_same<A, double>::value, "global partials are FP64");
+    const JkItem it = g.items[blockIdx.x];
+    if (g.only_active && g.state[it.mol].status != KS_MOL_ACTIVE) return;
+    const MolDesc md = g.mol[it.mol];
+    const int N = md.nbf, NN = N * N;
+    extern __shared__ __align__(16) unsigned char smem_jk[];
+    const double* Ps = g.dP + md.mat0;
+    double* AJ = (double*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+    double* AK = AJ + g.part_stride;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        AJ[i] = 0.0;
+        AK[i] = 0.0;
+    }
+    __syncthreads();
+    double* Prow = (double*)smem_jk;          // [6][N]
+    double* Krow = Prow + 6 * N;              // [6][N]
+    digest_class_rows<0, 0, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+    digest_class_rows<1, 0, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+    digest_class_rows<1, 0, 1, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+    digest_class_rows<1, 1, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+    digest_class_rows<1, 1, 1, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+    digest_class_rows<1, 1, 1, 1, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
+}
+
+// LDS-resident digestion of a subset of the quartet classes (bit c of CMASK
+// set: class c), with NTH threads per group: each class group gets its own
+// register allocation, so the classes of few components run with twice the
+// wavefronts of the (pp|pp)-bearing group.  The first group of a build
+// starts its partial J/K from zero, the later ones from the partial the
+// earlier groups wrote for the same work item.
+template <typename S, typename A, int CMASK, int NTH, bool FIRST>
+__global__ __launch_bounds__(NTH) void jk_class_kernel(JkArgs g)
 {
     const JkItem it = g.items[blockIdx.x];
     if (g.only_active && g.state[it.mol].status != KS_MOL_ACTIVE) return;
     const MolDesc md = g.mol[it.mol];
     const int N = md.nbf, NN = N * N;
     extern __shared__ __align__(16) unsigned char smem_jk[];
-    const A* Ps;
-    A *AJ, *AK;
-    if constexpr (GLOBAL) {
-        Ps = (const A*)(g.dP + md.mat0);
-        AJ = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
-        AK = AJ + g.part_stride;
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-            AJ[i] = A(0);
-            AK[i] = A(0);
-        }
-    } else {
-        A* Pl = (A*)smem_jk;
-        AJ = Pl + NN;
-        AK = AJ + NN;
-        const double* P = g.P + md.mat0;
-        const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-            Pl[i] = A(Pr ? P[i] - Pr[i] : P[i]);
-            AJ[i] = A(0);
-            AK[i] = A(0);
-        }
-        Ps = Pl;
+    A* Pl = (A*)smem_jk;
+    A* AJ = Pl + NN;
+    A* AK = AJ + NN;
+    const double* P = g.P + md.mat0;
+    const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
+    A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        Pl[i] = A(Pr ? P[i] - Pr[i] : P[i]);
+        AJ[i] = FIRST ? A(0) : out[i];
+        AK[i] = FIRST ? A(0) : out[g.part_stride + i];
     }
     __syncthreads();
-    if constexpr (GLOBAL) {
-        static_assert(std::is_same<A, double>::value, "global partials are FP64");
-        double* Prow = (double*)smem_jk;          // [6][N]
-        double* Krow = Prow + 6 * N;              // [6][N]
-        digest_class_rows<0, 0, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
-        digest_class_rows<1, 0, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
-        digest_class_rows<1, 0, 1, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
-        digest_class_rows<1, 1, 0, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
-        digest_class_rows<1, 1, 1, 0, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
-        digest_class_rows<1, 1, 1, 1, S>(g, md, it.chunk, it.nchunk, Ps, AJ, AK, Prow, Krow);
-        return;
-    }
-    digest_class<0, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
-    digest_class<1, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
-    digest_class<1, 0, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
-    digest_class<1, 1, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
-    digest_class<1, 1, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
-    digest_class<1, 1, 1, 1, S, A>(g, md, it.chunk, it.nchunk, Ps, AJ, AK);
-    if constexpr (!GLOBAL) {
-        __syncthreads();
-        A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
-        for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-            out[i] = AJ[i];
-            out[g.part_stride + i] = AK[i];
-        }
+    if constexpr ((CMASK & 1) != 0) digest_class<0, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
+    if constexpr ((CMASK & 2) != 0) digest_class<1, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
+    if constexpr ((CMASK & 4) != 0) digest_class<1, 0, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
+    if constexpr ((CMASK & 8) != 0) digest_class<1, 1, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
+    if constexpr ((CMASK & 16) != 0) digest_class<1, 1, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
+    if constexpr ((CMASK & 32) != 0) digest_class<1, 1, 1, 1, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
+    __syncthreads();
+    for (int i = threadIdx.x; i < NN; i += blockDim.x) {
+        out[i] = AJ[i];
+        out[g.part_stride + i] = AK[i];
     }
 }
+
+// Class groups: (ss|ss), (ps|ss), (ps|ps) need at most ~120 registers and
+// run 16 wavefronts per group; the classes with a pp pair run 8.
+constexpr int kJkLightMask = 1 | 2 | 4, kJkHeavyMask = 8 | 16 | 32;
+constexpr int kJkLightThreads = 1024, kJkHeavyThreads = 512;
 
 // dP = P - Pref (or P) for the global-mode digestion, active molecules only.
 __global__ void delta_kernel(const MolDesc* __restrict__ mols, const MolState* __restrict__ state, int only_active,
@@ -350,12 +383,20 @@ static ks_status run_jk(ks_batch* b, const double* P, double* J, double* K, bool
     g.part_stride = (long)b->max_np * b->max_np;
     g.only_active = only_active;
     const size_t lds = jk_lds_bytes(b);
-    KS_HIP(hipFuncSetAttribute((const void*)jk_kernel<S, A, GLOBAL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    {
+    const dim3 grid((unsigned)b->jk_items.size());
+    if constexpr (GLOBAL) {
+        KS_HIP(hipFuncSetAttribute((const void*)jk_kernel<S, A, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
         KTimer tm(b, "jk");
-        hipLaunchKernelGGL((jk_kernel<S, A, GLOBAL>), dim3((unsigned)b->jk_items.size()), dim3(kJkThreads), lds,
-                           b->stream, g);
+        hipLaunchKernelGGL((jk_kernel<S, A, true>), grid, dim3(kJkThreads), lds, b->stream, g);
+    } else {
+        auto light = jk_class_kernel<S, A, kJkLightMask, kJkLightThreads, true>;
+        auto heavy = jk_class_kernel<S, A, kJkHeavyMask, kJkHeavyThreads, false>;
+        KS_HIP(hipFuncSetAttribute((const void*)light, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        KS_HIP(hipFuncSetAttribute((const void*)heavy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        KTimer tm(b, "jk");
+        hipLaunchKernelGGL(light, grid, dim3(kJkLightThreads), lds, b->stream, g);
+        hipLaunchKernelGGL(heavy, grid, dim3(kJkHeavyThreads), lds, b->stream, g);
     }
     KS_HIP(hipGetLastError());
     return launch_jk_reduce(b, std::is_same<A, double>::value, P, J, K, only_active, incremental, track);
