@@ -56,9 +56,15 @@ typedef enum {
 
 typedef enum {
     KS_FP64 = 0,            /* every step in FP64 */
-    KS_MIXED = 1            /* ERIs, J/K and XC in FP32 with FP32 accumulation;
-                               Loewdin, eigensolve, DIIS, Fock assembly and the
-                               energy sum in FP64 */
+    KS_MIXED = 1            /* stored ERIs in FP32 (evaluated in FP64, rounded once
+                               on store); J/K digests the FP32 integrals against the
+                               FP64 density with FP64 accumulation (FP32 above 82
+                               functions); XC in FP32 (AO values, X = Phi P on FP32
+                               MFMAs, the functional) with Phi^T W on bf16 split pairs
+                               (operands within 2^-17 relative, FP32 accumulation)
+                               and E_XC summed per point in FP64; Loewdin,
+                               eigensolve, DIIS, Fock assembly and the energy sum in
+                               FP64 */
 } ks_precision;
 
 /* per-molecule status (ks_get_result) */

@@ -458,6 +458,46 @@ __device__ __forceinline__ f4_t mfma_pair(u32x4_t a, u32x4_t b, f4_t c)
 // four values along k are contiguous in LDS (one vector read) whenever the
 // operand is stored k-contiguous.
 
+// Sum over the four rows of 16 lanes, left in every lane: the gfx950
+// permlane swaps (v_permlane16_swap / v_permlane32_swap, VALU, no LDS
+// traffic) exchange odd and even rows, then the two halves of the wave; with
+// both operands the same value the two results add to x + x(lane ^ 16),
+// then to the sum over lane ^ 32.  FP64 values travel as two 32-bit halves.
+__device__ __forceinline__ float sum_rows(float x)
+{
+    const unsigned int u = __builtin_bit_cast(unsigned int, x);
+    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    x = __builtin_bit_cast(float, (unsigned int)a[0]) + __builtin_bit_cast(float, (unsigned int)a[1]);
+    const unsigned int v = __builtin_bit_cast(unsigned int, x);
+    const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __builtin_bit_cast(float, (unsigned int)b[0]) + __builtin_bit_cast(float, (unsigned int)b[1]);
+}
+__device__ __forceinline__ double swap_rows(double x, bool wide, double& other)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned int lo = (unsigned int)u, hi = (unsigned int)(u >> 32);
+    unsigned int a0, a1, b0, b1;
+    if (wide) {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a0 = l[0]; a1 = l[1]; b0 = h[0]; b1 = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a0 = l[0]; a1 = l[1]; b0 = h[0]; b1 = h[1];
+    }
+    other = __builtin_bit_cast(double, (unsigned long long)a1 | ((unsigned long long)b1 << 32));
+    return __builtin_bit_cast(double, (unsigned long long)a0 | ((unsigned long long)b0 << 32));
+}
+__device__ __forceinline__ double sum_rows(double x)
+{
+    double o;
+    double s = swap_rows(x, false, o);
+    x = s + o;
+    s = swap_rows(x, true, o);
+    return s + o;
+}
+
 // X^T tiles (t = wave + NW j, j < NJ; AO tile t / (BP/16), point tile
 // t % (BP/16)) of X^T = P Phi^T over K = NP, then, from the tile in
 // registers, this tile's share of rho = sum_mu X Phi and of
@@ -506,13 +546,10 @@ __device__ __forceinline__ void gemm_x_rho(const T* __restrict__ Pl, const T* __
             s2 += x * Phi[2 * PL + o];
             s3 += x * Phi[3 * PL + o];
         }
-#pragma unroll
-        for (int o = 16; o <= 32; o <<= 1) {
-            s0 += __shfl_xor(s0, o, 64);
-            s1 += __shfl_xor(s1, o, 64);
-            s2 += __shfl_xor(s2, o, 64);
-            s3 += __shfl_xor(s3, o, 64);
-        }
+        s0 = sum_rows(s0);
+        s1 = sum_rows(s1);
+        s2 = sum_rows(s2);
+        s3 = sum_rows(s3);
         if (q == 0) {
             T* rp = rpart + mt * 4 * BP + gpt;
             rp[0] = s0;
@@ -842,14 +879,28 @@ __global__ __launch_bounds__(NW * 64) void xc_kernel(XcArgs g)
             const T c0 = T(0.5) * w * vr, s2 = T(2) * w * vs;
             const T c1 = s2 * coef[4 * gp + 1], c2 = s2 * coef[4 * gp + 2], c3 = s2 * coef[4 * gp + 3];
             const int cw = (NP + NG - 1) / NG, m0 = grp * cw, m1 = min(NP, m0 + cw);
-            for (int mu = m0; mu < m1; mu++) {
+            // four AO rows at a time: all sixteen reads issued before the
+            // first use, so their LDS latency overlaps
+            int mu = m0;
+            for (; mu + 4 <= m1; mu += 4) {
                 T* o = Phi + mu * LDG + gp;
-                if constexpr (kPair) {
-                    const float w = c0 * o[0] + c1 * o[PL] + c2 * o[2 * PL] + c3 * o[3 * PL];
-                    *(unsigned int*)(o + PL) = bf16_pair(w);
-                } else {
-                    o[PL] = c0 * o[0] + c1 * o[PL] + c2 * o[2 * PL] + c3 * o[3 * PL];
+                T v[4][4];
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+#pragma unroll
+                    for (int k = 0; k < 4; k++) v[r][k] = o[r * LDG + k * PL];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const T wv = c0 * v[r][0] + c1 * v[r][1] + c2 * v[r][2] + c3 * v[r][3];
+                    if constexpr (kPair) *(unsigned int*)(o + r * LDG + PL) = bf16_pair(wv);
+                    else o[r * LDG + PL] = wv;
                 }
+            }
+            for (; mu < m1; mu++) {
+                T* o = Phi + mu * LDG + gp;
+                const T wv = c0 * o[0] + c1 * o[PL] + c2 * o[2 * PL] + c3 * o[3 * PL];
+                if constexpr (kPair) *(unsigned int*)(o + PL) = bf16_pair(wv);
+                else o[PL] = wv;
             }
         }
         __syncthreads();
