@@ -102,7 +102,9 @@ __device__ __forceinline__ void boys(R T, R (&F)[L + 1], const R* __restrict__ t
     } else {
         const R rt = rsqrt_nr(T);
         R e = exp(-T), inv = rt * rt;
-        F[0] = R(0.5 * 1.7724538509055160273) * rt;   // sqrt(pi) / 2 / sqrt(T)
+        // sqrt(pi) / 2 / sqrt(T), the constant applied in FP64 (an FP32 copy
+        // would bias every far-apart integral by its rounding)
+        F[0] = R((0.5 * 1.7724538509055160273) * (double)rt);
 #pragma unroll
         for (int m = 0; m < L; ++m) F[m + 1] = (R(2 * m + 1) * F[m] - e) * R(0.5) * inv;
     }
@@ -222,30 +224,38 @@ struct PairView {
 // ---------------------------------------------------------------------------
 // ROWS: tab is the Boys row table of L = LA + LB + LC + LD (boys_rows), else
 // the full table (boys) with BK Taylor terms (0: the type's default).
-template <int LA, int LB, int LC, int LD, typename R, bool ROWS = false, int PP = kNPrimPair, int BK = 0>
+// Acc: the accumulator type of the contracted integrals (FP64 for FP32
+// evaluation of the classes of few components, where it costs little).  The
+// prefactor 2 pi^(5/2) K_ab / p and K_cd / q are formed in FP64 per primitive
+// pair and rounded once each: an FP32 2 pi^(5/2) would scale every integral
+// by the same relative error (3e-8), a bias of ~1e-5 Ha in the energy.
+template <int LA, int LB, int LC, int LD, typename R, bool ROWS = false, int PP = kNPrimPair, int BK = 0,
+          typename Acc = R>
 __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, const Shell& sc, const Shell& sd,
                                             const PairView<PP>& vb, const PairView<PP>& vk, const R* __restrict__ tab,
-                                            R cut, R* acc)
+                                            R cut, Acc* acc)
 {
     constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
-    const R pi25 = R(2.0 * 17.493418327624862);   // 2 pi^(5/2)
+    constexpr double pi25 = 2.0 * 17.493418327624862;   // 2 pi^(5/2)
 #pragma unroll
-    for (int i = 0; i < NA * NB * NC * ND; i++) acc[i] = R(0);
+    for (int i = 0; i < NA * NB * NC * ND; i++) acc[i] = Acc(0);
     auto bra = [&](int ip) {
         const double bP[3] = {vb.get(1, ip), vb.get(2, ip), vb.get(3, ip)};
-        const R p = R(vb.get(0, ip)), Kb = R(vb.get(4, ip)), ipv = R(vb.get(5, ip));
+        const double ipd = vb.get(5, ip);
+        const R p = R(vb.get(0, ip)), Kbp = R(pi25 * vb.get(4, ip) * ipd), ipv = R(ipd);
         // negligible for every ket: q >= kQMin and |K_cd| <= kKMax bound the prefactor
-        if (fabs(Kb) * pi25 * R(kKMax / kQMin) * ipv * rsqrt_nr(p + R(kQMin)) < cut) return;
+        if (fabs(Kbp) * R(kKMax / kQMin) * rsqrt_nr(p + R(kQMin)) < cut) return;
         R eb[3][4][3];
         const R i2p = R(0.5) * ipv;
 #pragma unroll
         for (int d = 0; d < 3; d++) hermite_E<R>(R(bP[d] - sa.A[d]), R(bP[d] - sb.A[d]), i2p, eb[d]);
         auto ket = [&](int jp) {
             const double kP[3] = {vk.get(1, jp), vk.get(2, jp), vk.get(3, jp)};
-            const R q = R(vk.get(0, jp)), Kk = R(vk.get(4, jp)), iqv = R(vk.get(5, jp));
+            const double iqd = vk.get(5, jp);
+            const R q = R(vk.get(0, jp)), Kkq = R(vk.get(4, jp) * iqd), iqv = R(iqd);
             const R rs = rsqrt_nr(p + q);                 // 1/sqrt(p + q)
-            const R pref = pi25 * ipv * iqv * rs * Kb * Kk;
+            const R pref = Kbp * Kkq * rs;
             if (fabs(pref) < cut) return;
             R ek[3][4][3];
             const R i2q = R(0.5) * iqv;
@@ -315,7 +325,7 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
                                         if (t > sx || u > sy || v > sz || t + u + v > LAB) continue;
                                         val += eb[0][bx][t] * eb[1][by][u] * eb[2][bz][v] * H[t][u][v];
                                     }
-                            acc[((ia * NB + jb) * NC + kc) * ND + ld] += pref * val;
+                            acc[((ia * NB + jb) * NC + kc) * ND + ld] += Acc(pref * val);
                         }
                 }
         };
@@ -400,7 +410,6 @@ __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
 {
     constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
     constexpr int NCOMP = class_ncomp(C);
-    static_assert(std::is_same<R, double>::value, "integrals are evaluated in FP64");
     const long qg = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (qg >= g.nq) return;
     S* out = (S*)g.out;
@@ -417,13 +426,14 @@ __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
     }
     const Pair P1 = g.pb[ib], P2 = g.pk[ik];
     const Shell sa = g.shells[P1.sa], sb = g.shells[P1.sb], sc = g.shells[P2.sa], sd = g.shells[P2.sb];
-    R acc[NCOMP];
+    typedef typename std::conditional<(sizeof(R) == 4 && NCOMP <= 9), double, R>::type Acc;
+    Acc acc[NCOMP];
     const PairView<PP> vb{g.ppb, g.npb, ib}, vk{g.ppk, g.npk, ik};
     // integrals stored in FP32: five Taylor terms of the Boys function
     // (truncation below 0.025^5/5! ~ 1e-10 relative, far under the FP32
     // rounding of the stored value) instead of seven
-    eri_quartet<LA, LB, LC, LD, R, false, PP, sizeof(S) == 4 ? 5 : 0>(sa, sb, sc, sd, vb, vk, (const R*)g.tab,
-                                                                       R(g.cut), acc);
+    eri_quartet<LA, LB, LC, LD, R, false, PP, sizeof(S) == 4 ? 5 : 0, Acc>(sa, sb, sc, sd, vb, vk, (const R*)g.tab,
+                                                                            R(g.cut), acc);
 #pragma unroll
     for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
 }
@@ -1001,6 +1011,7 @@ ks_status launch_eri(ks_batch* b)
     if (b->pp == kPrimPairMax)
         return b->opt.prec == KS_MIXED ? launch_all_classes<double, float, kPrimPairMax>(b)
                                        : launch_all_classes<double, double, kPrimPairMax>(b);
+    if (b->opt.prec == KS_MIXED && b->max_np <= 96) return launch_all_classes<float, float, kNPrimPair>(b);
     if (b->opt.prec == KS_MIXED) return launch_all_classes<double, float, kNPrimPair>(b);
     return launch_all_classes<double, double, kNPrimPair>(b);
 }

@@ -7,10 +7,12 @@ and E_XC (paper section 3.1) element by element.
 
 Tolerances follow from the roundings of the mixed path, as bounds scaled by
 sums of absolute values (computed from the oracle's own quantities):
-- J, K: each integral is evaluated in FP64 and stored in FP32 (relative
-  rounding u = 2^-24), the density and the accumulation stay FP64, so
-  |dJ_mn| <= u sum_ls |(mn|ls)| |P_ls| (K likewise), taken as 2u plus the
-  1e-12 of the FP64 integrals and their prefactor screening per term.
+- J, K: each integral is evaluated in FP32 and stored in FP32; its error is
+  held to 2^-19 Q_mn Q_ls (16 units u = 2^-24 of FP32 rounding on the
+  quartet's Schwarz product Q_mn = sqrt((mn|mn)), from the oracle's
+  integrals; the same bound the integral test checks), the density and the
+  accumulation stay FP64, so |dJ_mn| <= 2^-19 Q_mn sum_ls Q_ls |P_ls| and
+  |dK_ml| <= 2^-19 sum_ns Q_mn |P_ns| Q_ls, plus 1e-12 per term.
 - V_XC: the Phi^T W product multiplies bf16 pairs (each operand within
   2^-17 relative, so 2^-16 per product term); the FP32 AO values carry
   |x| 1e-7 <= 4e-6 relative from the exponential at |x| <= 40 (2^-18 on
@@ -63,7 +65,15 @@ def case():
         P = dens["P_default_%d" % m]
         eri = o.eri()
         J, K = o.jk(eri, P)
-        BJ, BK = o.jk(np.abs(eri), np.abs(P))
+        N = o.nbf
+        npair = N * (N + 1) // 2
+        qp = np.sqrt(np.abs(eri[[q * (q + 1) // 2 + q for q in range(npair)]]))
+        Q = np.zeros((N, N))
+        iu, ju = np.tril_indices(N)
+        Q[iu, ju] = qp
+        Q[ju, iu] = qp
+        BJ = Q * np.sum(Q * np.abs(P))
+        BK = Q @ np.abs(P) @ Q
         grid = o.grid()
         exc, V = o.xc(O.XC_B3LYP, grid, P)
         A, SE = _xc_scales(o, grid, P)
@@ -116,8 +126,8 @@ def test_bench_kernels_vs_oracle(ks, case, prec):
         dJ, dK, dV = np.abs(J[m] - r["J"]), np.abs(K[m] - r["K"]), np.abs(V[m] - r["V"])
         dE = abs(exc[m] - r["exc"])
         if prec == 1:
-            tJ = 2 * u * r["BJ"] + 1e-12 * r["Psum"]
-            tK = 2 * u * r["BK"] + 1e-12 * r["Psum"]
+            tJ = 2.0 ** -19 * r["BJ"] + 1e-12 * r["Psum"]
+            tK = 2.0 ** -19 * r["BK"] + 1e-12 * r["Psum"]
             tV = eps_v * r["A"] + 1e-14
             tE = eps_e * r["SE"]
         else:

@@ -81,29 +81,45 @@ def test_eri_packed(small):
 
 
 def test_eri_mixed(ks):
-    # The mixed path evaluates the integrals in FP64, skips primitive quartets
-    # whose prefactor is below 1e-14 (at most 81 per contracted quartet, each
-    # bounded by its prefactor), and stores them in FP32 (half an ulp:
-    # 6e-8 |I|), so |dI| <= 1e-12 + 6e-8 |I|.
+    # The mixed path evaluates the integrals of molecules up to 96 functions
+    # in FP32 (prefactors formed in FP64 and rounded once, accumulation in
+    # FP64 for classes of up to 9 components), skips primitive quartets whose
+    # prefactor is below 1e-14, and stores them in FP32.  Every primitive
+    # term carries about ten roundings and the contraction up to 81 terms;
+    # the terms of a quartet are bounded by its Schwarz product Q_ab Q_cd
+    # (Q_ab = sqrt((ab|ab)), from the oracle), so the error is held to
+    # 2^-19 Q_ab Q_cd (16 units of FP32 rounding) plus 1e-12.
+    tol_u = 2.0 ** -19
     mols = _mols_small() + [molgen.tree(9, 1, 0)]
+    worst = 0.0
     with ks.Batch(mols, prec=ks.KS_MIXED) as b:
         b.eri_build()
         for m, (z, x) in enumerate(mols):
             o = O.Mol(z, x)
             got = b.eri(m)
+            N = o.nbf
+            pid = lambda i, j: i * (i + 1) // 2 + j if i >= j else j * (j + 1) // 2 + i
             if m < len(mols) - 1:
                 ref = o.eri()
-                assert np.all(np.abs(got - ref) <= 1e-12 + 6e-8 * np.abs(ref)), m
+                npair = N * (N + 1) // 2
+                Q = np.sqrt(np.abs(ref[[p * (p + 1) // 2 + p for p in range(npair)]]))
+                ij, kl = np.tril_indices(npair)
+                bound = tol_u * Q[ij] * Q[kl] + 1e-12
+                d = np.abs(got - ref)
+                worst = max(worst, float((d / bound).max()))
+                assert np.all(d <= bound), m
                 continue
             rng = np.random.default_rng(6)
-            N = o.nbf
             for _ in range(2000):
                 i, j, k, l = (int(v) for v in rng.integers(0, N, 4))
-                ij = i * (i + 1) // 2 + j if i >= j else j * (j + 1) // 2 + i
-                kl = k * (k + 1) // 2 + l if k >= l else l * (l + 1) // 2 + k
+                ij, kl = pid(i, j), pid(k, l)
                 idx = ij * (ij + 1) // 2 + kl if ij >= kl else kl * (kl + 1) // 2 + ij
                 ref = o.eri_one(i, j, k, l)
-                assert abs(got[idx] - ref) <= 1e-12 + 6e-8 * abs(ref), (i, j, k, l, got[idx], ref)
+                qq = np.sqrt(abs(o.eri_one(i, j, i, j)) * abs(o.eri_one(k, l, k, l)))
+                bound = tol_u * qq + 1e-12
+                worst = max(worst, abs(got[idx] - ref) / bound)
+                assert abs(got[idx] - ref) <= bound, (i, j, k, l, got[idx], ref)
+    print("mixed ERIs: largest error %.3f of the bound" % worst, flush=True)
 
 
 def test_grid(small):
