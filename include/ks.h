@@ -105,6 +105,10 @@ typedef struct {
                                second iteration, so results are those of the main grid.  Each count at
                                most the main grid's.  Measured best for 9-11-heavy-atom molecules on the
                                50 x 12 x 24 grid: 25 x 8 x 16. */
+    int eri_threads[6];     /* ERI launch shape per quartet class ((ss|ss), (ps|ss), (ps|ps), (pp|ss),
+                               (pp|ps), (pp|pp)): work-group size 64, 128 or 256 (0 = 128) */
+    int eri_unroll[6];      /* the same classes: ket primitive pairs evaluated per unrolled group, 3 or
+                               9 (0 = 3; STO-3G; 6-31G loops over each shell pair's real pairs) */
 } ks_options;
 
 /* Initial density.  The paper only says C_1 is initialised (section 3.1).

@@ -3,8 +3,9 @@
 For a workload (number of molecules, heavy-atom range, precision) it times,
 with HIP events on the batch stream, the XC kernel over its launch shapes
 (grid points per sub-block x wavefronts per work group) and work-group counts
-per molecule, and the J/K digestion over its work-group counts per molecule,
-on the molecules' initial densities.  The best settings are stored in a JSON
+per molecule, the J/K digestion over its work-group counts per molecule, on
+the molecules' initial densities, and the ERI class kernels over their
+work-group size and ket-loop unroll (each quartet class separately).  The best settings are stored in a JSON
 table keyed by precision, basis-size bucket (largest N rounded up to 16) and
 batch-size bucket; `tuned_options` returns the entry closest to a batch.
 
@@ -23,6 +24,9 @@ TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 XC_SHAPES = [(64, 8), (64, 16), (32, 8), (32, 16), (16, 8), (64, 4), (32, 4)]
 XC_CHUNKS = [16, 32, 64]
 JK_CHUNKS = [2, 4, 8, 16]
+ERI_THREADS = [64, 128, 256]
+ERI_UNROLL = [3, 9]
+ERI_CLASSES = ["ssss", "psss", "psps", "ppss", "ppps", "pppp"]
 
 
 def _bucket_np(nbf_max: int) -> int:
@@ -63,7 +67,8 @@ def tuned_options(prec: int, nbf, path: str = TABLE) -> dict:
             best, dist = v, d
     if not best:
         return {}
-    return {k: best[k] for k in ("xc_points", "xc_waves", "xc_chunks", "jk_chunks")}
+    keys = ("xc_points", "xc_waves", "xc_chunks", "jk_chunks", "eri_threads", "eri_unroll")
+    return {k: best[k] for k in keys if k in best}
 
 
 def _time_xc(ks, mols, prec, pts, waves, chunks, reps):
@@ -94,6 +99,44 @@ def _time_jk(ks, mols, prec, chunks, reps):
     return ms
 
 
+def _time_eri(ks, mols, prec, threads, unroll, reps):
+    """Per-class ERI kernel times (ms) of eri_build with these launch shapes,
+    the grid and one-electron set-up finished first; median of reps builds."""
+    import torch
+    runs = []
+    for _ in range(reps):
+        b = ks.Batch(mols, prec=prec, eri_threads=threads, eri_unroll=unroll)
+        b.setup()
+        torch.cuda.synchronize()
+        b.set_timing(True)
+        b.eri_build()
+        kt = b.kernel_times()
+        runs.append([kt["eri_" + c][0] if ("eri_" + c) in kt else 0.0 for c in ERI_CLASSES])
+        b.close()
+    runs.sort(key=sum)
+    return runs[len(runs) // 2]
+
+
+def tune_eri(ks, mols, prec, reps=3, log=print):
+    """Work-group size and ket unroll per quartet class: every (threads,
+    unroll) pair is timed for all classes at once (the classes are separate
+    launches), and each class keeps its fastest pair."""
+    res = []
+    for t in ERI_THREADS:
+        for u in ERI_UNROLL:
+            ms = _time_eri(ks, mols, prec, [t] * 6, [u] * 6, reps)
+            res.append((t, u, ms))
+            log("eri threads %3d unroll %d: %s (sum %.2f ms)" % (t, u, " ".join("%.2f" % v for v in ms), sum(ms)))
+    threads, unroll, best_ms = [], [], []
+    for c in range(6):
+        t, u, ms = min(res, key=lambda r: r[2][c])
+        threads.append(t)
+        unroll.append(u)
+        best_ms.append(ms[c])
+    base = next(r[2] for r in res if r[0] == 128 and r[1] == 3)
+    return dict(eri_threads=threads, eri_unroll=unroll, eri_ms=sum(best_ms), eri_ms_default=sum(base)), res
+
+
 def tune(ks, mols, prec, reps=3, log=print, shapes=None, xc_chunks=None, jk_chunks=None):
     res = {"xc": [], "jk": []}
     for pts, waves in shapes or XC_SHAPES:
@@ -109,6 +152,8 @@ def tune(ks, mols, prec, reps=3, log=print, shapes=None, xc_chunks=None, jk_chun
     bj = min(res["jk"], key=lambda r: r["ms"])
     best = dict(xc_points=bx["xc_points"], xc_waves=bx["xc_waves"], xc_chunks=bx["xc_chunks"],
                 jk_chunks=bj["jk_chunks"], xc_ms=bx["ms"], jk_ms=bj["ms"])
+    be, res["eri"] = tune_eri(ks, mols, prec, reps, log)
+    best.update(be)
     return best, res
 
 
@@ -123,6 +168,8 @@ def main():
     ap.add_argument("--xc-shapes", default="", help="points x waves list, e.g. 64x16,64x8 (default: all)")
     ap.add_argument("--xc-chunks", default="", help="work groups per molecule list, e.g. 32,64 (default: all)")
     ap.add_argument("--jk-chunks", default="", help="J/K work groups per molecule list (default: all)")
+    ap.add_argument("--eri-only", action="store_true",
+                    help="tune only the ERI launch shapes and merge them into the existing entry")
     a = ap.parse_args()
     sys.path.insert(0, ROOT)
     import torch
@@ -134,11 +181,19 @@ def main():
     shapes = [tuple(int(v) for v in t.split("x")) for t in a.xc_shapes.split(",")] if a.xc_shapes else None
     xcc = [int(v) for v in a.xc_chunks.split(",")] if a.xc_chunks else None
     jkc = [int(v) for v in a.jk_chunks.split(",")] if a.jk_chunks else None
-    best, res = tune(ks, mols, prec, a.reps, log=lambda s: print(s, flush=True), shapes=shapes, xc_chunks=xcc,
-                     jk_chunks=jkc)
     nbf = [molgen.nbf_sto3g(z) for z, _ in mols]
     table = load_table(a.out)
-    table[key(prec, max(nbf), len(mols))] = dict(best, workload="%d x %s heavy, seed %d" % (a.n_mol, a.heavy, a.seed))
+    k = key(prec, max(nbf), len(mols))
+    if a.eri_only:
+        best, _ = tune_eri(ks, mols, prec, a.reps, log=lambda s: print(s, flush=True))
+        entry = dict(table.get(k, {}))
+        entry.update(best)
+        entry.setdefault("workload", "%d x %s heavy, seed %d" % (a.n_mol, a.heavy, a.seed))
+        table[k] = entry
+    else:
+        best, res = tune(ks, mols, prec, a.reps, log=lambda s: print(s, flush=True), shapes=shapes, xc_chunks=xcc,
+                         jk_chunks=jkc)
+        table[k] = dict(best, workload="%d x %s heavy, seed %d" % (a.n_mol, a.heavy, a.seed))
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
     print("best", json.dumps(best))

@@ -386,6 +386,13 @@ static ks_status create_impl(const ks_options* opt_in, int n_mol, const int* n_a
         set_error("unknown xc or precision option");
         return KS_EINVAL;
     }
+    for (int c = 0; c < kNClass; c++) {
+        const int t = opt.eri_threads[c], u = opt.eri_unroll[c];
+        if ((t != 0 && t != 64 && t != 128 && t != 256) || (u != 0 && u != 3 && u != 9)) {
+            set_error("eri_threads must be 0, 64, 128 or 256 and eri_unroll 0, 3 or 9 (class %d: %d, %d)", c, t, u);
+            return KS_EINVAL;
+        }
+    }
     if ((opt.direct != 0 && opt.direct != 1) || !(opt.schwarz_tol >= 0.0) || (opt.graphs != 0 && opt.graphs != 1)) {
         set_error("direct and graphs must be 0 or 1 and schwarz_tol >= 0");
         return KS_EINVAL;

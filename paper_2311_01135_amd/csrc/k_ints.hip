@@ -230,7 +230,7 @@ struct PairView {
 // pair and rounded once each: an FP32 2 pi^(5/2) would scale every integral
 // by the same relative error (3e-8), a bias of ~1e-5 Ha in the energy.
 template <int LA, int LB, int LC, int LD, typename R, bool ROWS = false, int PP = kNPrimPair, int BK = 0,
-          typename Acc = R>
+          typename Acc = R, int UNR = 3>
 __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, const Shell& sc, const Shell& sd,
                                             const PairView<PP>& vb, const PairView<PP>& vk, const R* __restrict__ tab,
                                             R cut, Acc* acc)
@@ -329,13 +329,18 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
                         }
                 }
         };
-        // STO-3G: nine ket primitive pairs, unrolled by three (fully
-        // unrolled, the ket data of all nine stay in registers and the class
-        // kernels drop to two or three waves per SIMD: 467 -> 385 ms for the
-        // ERIs of 2048 molecules); 6-31G: the real pairs in a plain loop
+        // STO-3G: nine ket primitive pairs in groups of UNR, each group
+        // unrolled (by default three: fully unrolled FP64 kernels keep all
+        // nine pairs' data in registers and drop to two or three waves per
+        // SIMD, 467 -> 385 ms for the ERIs of 2048 molecules; the autotuner
+        // picks per class); 6-31G: the real pairs in a plain loop
         if constexpr (PP <= kNPrimPair) {
-#pragma unroll 3
-            for (int jp = 0; jp < PP; jp++) ket(jp);
+            static_assert(PP % UNR == 0, "ket groups");
+#pragma unroll 1
+            for (int j0 = 0; j0 < PP; j0 += UNR) {
+#pragma unroll
+                for (int u = 0; u < UNR; u++) ket(j0 + u);
+            }
         } else {
             const int nk = sc.np * sd.np;       // the ket's real primitive pairs
 #pragma unroll 1
@@ -403,10 +408,11 @@ struct EriArgs {
 // group made the class kernels 15% faster alone, but beside the grid kernel
 // on the other stream the two compete for LDS and the pair finished no
 // earlier.)
-constexpr int kEriThreads = 128;
+// Work-group size per class: the options' (64, 128 or 256; autotuned), else 128.
+constexpr int kEriThreads = 128, kEriThreadsMax = 256;
 
-template <int LA, int LB, int LC, int LD, typename R, typename S, int PP>
-__global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
+template <int LA, int LB, int LC, int LD, typename R, typename S, int PP, int UNR = 3>
+__global__ __launch_bounds__(kEriThreadsMax) void eri_class_kernel(EriArgs g)
 {
     constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
     constexpr int NCOMP = class_ncomp(C);
@@ -432,8 +438,8 @@ __global__ __launch_bounds__(kEriThreads) void eri_class_kernel(EriArgs g)
     // integrals stored in FP32: five Taylor terms of the Boys function
     // (truncation below 0.025^5/5! ~ 1e-10 relative, far under the FP32
     // rounding of the stored value) instead of seven
-    eri_quartet<LA, LB, LC, LD, R, false, PP, sizeof(S) == 4 ? 5 : 0, Acc>(sa, sb, sc, sd, vb, vk, (const R*)g.tab,
-                                                                            R(g.cut), acc);
+    eri_quartet<LA, LB, LC, LD, R, false, PP, sizeof(S) == 4 ? 5 : 0, Acc, UNR>(sa, sb, sc, sd, vb, vk,
+                                                                                 (const R*)g.tab, R(g.cut), acc);
 #pragma unroll
     for (int k = 0; k < NCOMP; k++) out[(size_t)k * g.nq + qg] = (S)acc[k];
 }
@@ -983,9 +989,19 @@ static ks_status launch_class(ks_batch* b, int c)
     g.Qb = b->d_Q[class_bra(c)];
     g.Qk = b->d_Q[class_ket(c)];
     g.schwarz = b->schwarz_done ? b->opt.schwarz_tol : 0.0;
-    const long nb = (g.nq + kEriThreads - 1) / kEriThreads;
-    hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S, PP>), dim3((unsigned)nb), dim3(kEriThreads), 0,
-                       b->stream, g);
+    const int nt = b->opt.eri_threads[c] > 0 ? b->opt.eri_threads[c] : kEriThreads;
+    const long nb = (g.nq + nt - 1) / nt;
+    static const char* const kClassTimer[kNClass] = {"eri_ssss", "eri_psss", "eri_psps", "eri_ppss", "eri_ppps",
+                                                      "eri_pppp"};
+    KTimer tc(b, kClassTimer[c]);
+    // the ket-loop unroll of the options (autotuned; 9 = fully unrolled) for
+    // the STO-3G table, else by three
+    if (PP == kNPrimPair && b->opt.eri_unroll[c] == 9)
+        hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S, PP, (PP == kNPrimPair ? 9 : 3)>),
+                           dim3((unsigned)nb), dim3(nt), 0, b->stream, g);
+    else
+        hipLaunchKernelGGL((eri_class_kernel<LA, LB, LC, LD, R, S, PP, 3>), dim3((unsigned)nb), dim3(nt), 0,
+                           b->stream, g);
     KS_HIP(hipGetLastError());
     return KS_OK;
 }

@@ -50,7 +50,8 @@ class Options(C.Structure):
                 ("xc_chunks", C.c_int), ("guess", C.c_int), ("xc_points", C.c_int),
                 ("xc_waves", C.c_int), ("direct", C.c_int), ("schwarz_tol", C.c_double),
                 ("basis", C.c_int), ("graphs", C.c_int), ("coarse_rad", C.c_int),
-                ("coarse_theta", C.c_int), ("coarse_phi", C.c_int)]
+                ("coarse_theta", C.c_int), ("coarse_phi", C.c_int), ("eri_threads", C.c_int * 6),
+                ("eri_unroll", C.c_int * 6)]
 
 
 _lib = None
@@ -132,6 +133,8 @@ def default_options(**kw) -> Options:
     o = Options()
     load().ks_default_options(C.byref(o))
     for k, v in kw.items():
+        if isinstance(v, (list, tuple)):
+            v = (C.c_int * len(v))(*v)
         setattr(o, k, v)
     return o
 

@@ -288,3 +288,29 @@ def test_eri_sampled_full_size(ks):
         kl = k * (k + 1) // 2 + l if k >= l else l * (l + 1) // 2 + k
         idx = ij * (ij + 1) // 2 + kl if ij >= kl else kl * (kl + 1) // 2 + ij
         assert abs(eri[idx] - o.eri_one(i, j, k, l)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_eri_launch_shapes(ks, prec):
+    """The per-class ERI launch shapes (work-group size, ket unroll) that the
+    autotuner chooses leave each contracted integral's arithmetic unchanged:
+    every shape gives the same packed integrals (to one rounding of the
+    stored type, should the compiler contract a product differently)."""
+    mols = _mols_small()
+    ref = None
+    for t, u in ((128, 3), (64, 9), (256, 3), (256, 9)):
+        with ks.Batch(mols, prec=prec, eri_threads=[t] * 6, eri_unroll=[u] * 6) as b:
+            b.eri_build()
+            got = [b.eri(m) for m in range(len(mols))]
+        if ref is None:
+            ref = got
+            continue
+        eps = 2.0 ** -23 if prec == 1 else 2.0 ** -52
+        for m, (a, r) in enumerate(zip(got, ref)):
+            d = np.abs(a - r)
+            print("shape %d x %d, molecule %d: max |dI| %.3e" % (t, u, m, d.max()), flush=True)
+            assert np.all(d <= 2 * eps * np.abs(r) + 1e-300), (t, u, m)
+    with pytest.raises(ks.KsError):
+        ks.Batch(mols, prec=prec, eri_threads=[100] * 6)
+    with pytest.raises(ks.KsError):
+        ks.Batch(mols, prec=prec, eri_unroll=[4] * 6)
