@@ -33,8 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "SCF solves/sec, 9–11 heavy atoms, FP32 vs FP64 (|ΔE|≤1e-4 Ha); p99 latency"
-PEAK = {"f64": 78.6, "f32": 157.3}     # MI355X dense MFMA TFLOP/s (FP64, FP32)
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # MI355X dense MFMA TFLOP/s (FP64, FP32, bf16)
 HBM_PEAK = 8000.0                      # GB/s
+SCREENING = os.path.join(ROOT, "tests", "golden", "xc_screening_seed2.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "xc_kernel_traffic.json")
 XC_SOURCE = os.path.join(ROOT, "paper_2311_01135_amd", "csrc", "k_xc.hip")
 
@@ -53,7 +54,10 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=0, help="molecules in the oracle sample (0 = one per thread)")
     p.add_argument("--jk-chunks", type=int, default=0)
     p.add_argument("--xc-chunks", type=int, default=0)
-    p.add_argument("--serve-requests", type=int, default=512, help="serving leg requests (0 = skip)")
+    p.add_argument("--serve-requests", type=int, default=20000, help="serving leg requests (0 = skip)")
+    p.add_argument("--serve-saturation", type=int, default=4096,
+                   help="requests of the saturated run that sets the Poisson arrival rate (first of the serving set)")
+    p.add_argument("--no-configs", action="store_true", help="skip the water and 256 x 9-heavy-atom FP64 legs")
     p.add_argument("--grid", type=str, default="50,12,24", help="radial,theta,phi points per atom")
     p.add_argument("--coarse-grid", type=str, default="25,8,16",
                    help="radial,theta,phi of the coarse start grid (0,0,0 = none); results stay the main grid's")
@@ -67,6 +71,32 @@ def parse():
     return p.parse_args()
 
 
+def _gen_chunk(job):
+    from paper_2311_01135_amd import molgen
+    n, seed, heavy, start, f_free = job
+    if f_free:
+        return molgen.batch_without(n, seed, heavy)
+    return molgen.batch(n, seed, heavy, start=start)
+
+
+def gen_batch(n, seed, heavy, f_free=False, workers=None):
+    """molgen.batch(n, seed, heavy) generated in chunks on a process pool
+    (each molecule has its own random stream, so the chunks give the same
+    molecules); run before anything touches the GPU."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    if f_free:
+        return _gen_chunk((n, seed, heavy, 0, True))
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    step = max(64, (n + 4 * workers - 1) // (4 * workers))
+    jobs = [(min(step, n - s0), seed, heavy, s0, False) for s0 in range(0, n, step)]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        out = []
+        for part in ex.map(_gen_chunk, jobs):
+            out += part
+    return out
+
+
 def heavy_range(s):
     if "-" in s:
         lo, hi = s.split("-")
@@ -74,12 +104,13 @@ def heavy_range(s):
     return int(s)
 
 
-def xc_flops(nbf, ngrid, niter, ngridc=None, ncoarse=None):
+def xc_flops(nbf, ngrid, niter, ngridc=None, ncoarse=None, r_main=1.0, r_coarse=1.0):
     """Algorithmic XC GEMM flops: 2 G N^2 for X = Phi P plus 2 G N^2 for Phi^T W, per iteration
-    (G of the coarse start grid for the iterations that ran on it)."""
+    (G of the coarse start grid for the iterations that ran on it); with r_main / r_coarse < 1 the
+    screened count (the dense work of each grid scaled by its screened fraction)."""
     ngridc = ngridc or [0] * len(nbf)
     ncoarse = ncoarse or [0] * len(nbf)
-    return float(sum(4.0 * n * n * (g * (it - ic) + gc * ic)
+    return float(sum(4.0 * n * n * (r_main * g * (it - ic) + r_coarse * gc * ic)
                      for n, g, it, gc, ic in zip(nbf, ngrid, niter, ngridc, ncoarse)))
 
 
@@ -102,6 +133,23 @@ def measured_traffic(args, prec_name):
     if args.basis != "sto-3g" or args.direct or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24):
         return None
     return t["traffic_bytes_per_launch"]
+
+
+def screened_ratio(args):
+    """Ratio of the screened XC GEMM work sum_b G_b N_b^2 (N_b: AOs above
+    1e-10 in 64-point block b) to the dense 4 G N^2, from the committed
+    oracle-based estimate for the benchmark molecules; None for other
+    workloads.  The kernel itself does the dense work."""
+    if (not os.path.exists(SCREENING) or args.seed != 2 or heavy_range(args.heavy) != (9, 11)
+            or args.basis != "sto-3g" or grid_shape(args) != (50, 12, 24)):
+        return None
+    if args.coarse_grid not in ("0,0,0", "25,8,16"):
+        return None
+    with open(SCREENING) as f:
+        d = json.load(f)
+    return dict(main=d["ratio_main"], coarse=d["ratio_coarse"],
+                source="tests/golden/xc_screening_seed2.json (molecules 0-%d, tau %g, %d-point blocks)"
+                % (len(d["molecules"]) - 1, d["tau"], d["block_points"]))
 
 
 def copy_calibration(torch, mib):
@@ -249,23 +297,88 @@ def serve_run(ks, reqs, arrivals, prec, **options):
     return wall, lat, rejected, iters
 
 
-def serving_leg(ks, args):
-    """Serving workload: 3-11 heavy atoms, mixed precision; saturated
-    throughput first, then Poisson arrivals at 0.8 x that rate."""
-    from paper_2311_01135_amd import molgen
-    n = args.serve_requests
-    reqs = molgen.batch(n, 3, (3, 11))
-    wall_sat, _, rej_sat, _ = serve_run(ks, reqs, np.zeros(n), ks.KS_MIXED, **coarse_options(args))
-    sat = (n - rej_sat) / wall_sat
+def serving_leg(ks, args, reqs):
+    """Serving workload: 3-11 heavy atoms (seed 3), mixed precision; the
+    saturated throughput of the first requests submitted at once sets the
+    rate, then all requests arrive as a Poisson stream at 0.8 x that rate."""
+    n = len(reqs)
+    ns = min(n, args.serve_saturation)
+    wall_sat, _, rej_sat, _ = serve_run(ks, reqs[:ns], np.zeros(ns), ks.KS_MIXED, **coarse_options(args))
+    sat = (ns - rej_sat) / wall_sat
     lam = 0.8 * sat
     rng = np.random.default_rng(3)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
     wall, lat, rej, iters = serve_run(ks, reqs, arrivals, ks.KS_MIXED, **coarse_options(args))
     ok = lat[np.isfinite(lat)]
-    return dict(requests=n, heavy_atoms="3-11", precision="mixed", saturated_solves_per_s=sat,
-                arrival_rate_per_s=lam, solves_per_s=len(ok) / wall, p50_latency_s=float(np.percentile(ok, 50)),
-                p99_latency_s=float(np.percentile(ok, 99)), max_latency_s=float(ok.max()),
-                rejected=int(rej + rej_sat), mean_iterations=float(iters[np.isfinite(lat)].mean()))
+    return dict(requests=n, heavy_atoms="3-11", precision="mixed", saturation_requests=ns,
+                saturated_solves_per_s=sat, arrival_rate_per_s=lam, solves_per_s=len(ok) / wall,
+                wall_s=wall, p50_latency_s=float(np.percentile(ok, 50)), p99_latency_s=float(np.percentile(ok, 99)),
+                max_latency_s=float(ok.max()), rejected=int(rej + rej_sat),
+                mean_iterations=float(iters[np.isfinite(lat)].mean()))
+
+
+def config_legs(ks, torch, water, c1, args):
+    """The small workloads: one water molecule (FP64, seed 0) solved alone,
+    its time per solve and |dE|, |d gap| against the stored oracle result; a
+    batch of 256 nine-heavy-atom molecules (FP64, seed 1) with its solves/s
+    and ERI rates.  Main grid only (no coarse start), default options."""
+    out = {}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_scf_samples.json")
+    with ks.Batch(water) as b:             # warm-up
+        b.scf_solve()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        with ks.Batch(water) as b:
+            b.scf_solve()
+            r = b.result(0)
+        ts.append(time.perf_counter() - t0)
+    w = dict(workload="water, B3LYP/STO-3G, FP64, grid 50x12x24, seed 0", s_per_solve_median=float(np.median(ts)),
+             E=r["E"], gap=r["gap"], n_iter=r["n_iter"])
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)["water_seed0"]
+        w.update(abs_dE_vs_oracle=abs(r["E"] - g["E"]), abs_dgap_vs_oracle=abs(r["gap"] - g["gap"]),
+                 oracle_n_iter=g["n_iter"])
+    out["water"] = w
+    from paper_2311_01135_amd import autotune, molgen
+    opts = autotune.tuned_options(ks.KS_FP64, [molgen.nbf_sto3g(z) for z, _ in c1])
+    with ks.Batch(c1, **opts) as b:        # warm-up
+        b.scf_solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with ks.Batch(c1, **opts) as b:
+        b.set_timing(True)
+        b.scf_solve()
+        res = b.results(density=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = b.kernel_times()
+        nq, nprim = b.quartets()
+        neri = float(sum(b.n_eri))
+    eri_ms = kt.get("eri", (float("nan"), 1))[0]
+    out["fp64_256x9"] = dict(workload="256 molecules, 9 heavy atoms, B3LYP/STO-3G, FP64, grid 50x12x24, seed 1",
+                             solves_per_s=len(c1) / wall, s_per_batch=wall,
+                             iterations_mean=float(np.mean([x["n_iter"] for x in res])),
+                             unconverged=int(sum(x["status"] != 1 for x in res)),
+                             eri_unique_shell_quartets_per_s=nq / (eri_ms * 1e-3),
+                             eri_unique_integrals_per_s=neri / (eri_ms * 1e-3), eri_ms=eri_ms)
+    print("configs: water %.1f ms/solve |dE| %.1e; 256x9 FP64 %.1f solves/s"
+          % (w["s_per_solve_median"] * 1e3, w.get("abs_dE_vs_oracle", float("nan")),
+             out["fp64_256x9"]["solves_per_s"]), file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(mols, args):
@@ -275,10 +388,13 @@ def cpu_baseline(mols, args):
     n = args.cpu_sample or nthreads
     sample = mols[:n]
     out = [None] * len(sample)
+    per = [0.0] * len(sample)
 
     def work(i):
         z, x = sample[i]
+        t = time.perf_counter()
         out[i] = O.Mol(z, x).scf(xc=O.XC_B3LYP)
+        per[i] = time.perf_counter() - t
 
     t0 = time.perf_counter()
     idx = list(range(len(sample)))
@@ -299,8 +415,10 @@ def cpu_baseline(mols, args):
         t.join()
     wall = time.perf_counter() - t0
     return dict(value=len(sample) / wall, unit="solves/s", cores=min(nthreads, len(sample)), kind="oracle",
-                sample="first %d molecules of the batch, full FP64 SCF each, one per thread, %.1f s wall"
-                       % (len(sample), wall)), out
+                cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+                median_s_per_molecule_one_thread=float(np.median(per)),
+                sample="first %d molecules of the batch, full FP64 SCF each (integrals, grid, every iteration), "
+                       "one per thread, %.1f s wall" % (len(sample), wall)), out
 
 
 def main():
@@ -309,19 +427,26 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    from paper_2311_01135_amd import molgen
+    # every input is generated before anything touches the GPU (process pool)
+    heavy = heavy_range(args.heavy)
+    t_gen = time.perf_counter()
+    mols = gen_batch(args.n_mol, args.seed, heavy, f_free=args.basis == "6-31g")
+    reqs = gen_batch(args.serve_requests, 3, (3, 11)) if args.serve_requests > 0 else []
+    legs = not args.no_configs and args.basis == "sto-3g"
+    water = [molgen.water(0)] if legs else []
+    c1 = gen_batch(256, 1, 9) if legs else []
+    print("generated %d + %d + %d molecules in %.1f s" % (len(mols), len(reqs), len(c1), time.perf_counter() - t_gen),
+          file=sys.stderr, flush=True)
+
     import torch
-    from paper_2311_01135_amd import ks, molgen
+    from paper_2311_01135_amd import ks
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
     ks.load()
-    heavy = heavy_range(args.heavy)
-    t_gen = time.perf_counter()
-    mols = (molgen.batch_without(args.n_mol, args.seed, heavy) if args.basis == "6-31g"
-            else molgen.batch(args.n_mol, args.seed, heavy))
-    print("generated %d molecules in %.1f s" % (len(mols), time.perf_counter() - t_gen), file=sys.stderr, flush=True)
 
     main_prec = ks.KS_FP64 if args.fp64_only else ks.KS_MIXED
     if args.copy_calibration_mib:
@@ -342,7 +467,12 @@ def main():
         t64, times64, (res64, kt64, _) = run_path(ks, torch, mols, ks.KS_FP64, args, 1, 0)
         dE = np.array([abs(a["E"] - b["E"]) for a, b in zip(res, res64)])
         dg = np.array([abs(a["gap"] - b["gap"]) for a, b in zip(res, res64)])
+        it64 = [r["n_iter"] for r in res64]
         fp64 = dict(value=args.n_mol / t64, unit="solves/s", s_per_batch=t64,
+                    iterations={"mean": float(np.mean(it64)), "max": int(max(it64)),
+                                "coarse_grid_mean": float(np.mean([r["n_coarse"] for r in res64]))},
+                    stopping="dE < 1e-9 Ha and commutator < 1e-7 (the mixed path stops at 1e-6 Ha and 1e-5, "
+                             "the resolution of its FP32 Fock matrix)",
                     kernel_ms={k: v[0] for k, v in kt64.items()})
         acc = dict(max_abs_dE_vs_fp64_gpu=float(dE.max()), p99_abs_dE=float(np.percentile(dE, 99)),
                    max_abs_dgap_vs_fp64_gpu=float(dg.max()), n_over_1e4=int(((dE > 1e-4) | (dg > 1e-4)).sum()),
@@ -361,8 +491,21 @@ def main():
     fl = xc_flops(info["nbf"], info["ngrid"], niter, ngridc, ncoarse)
     achieved = fl / max(1, xc_launches) / (xc_ms * 1e-3) / 1e12 if xc_launches else float("nan")
     dtype = "f64" if main_prec == ks.KS_FP64 else "f32"
+    # against each contraction's own peak: X = Phi P on FP32 MFMAs, Phi^T W on
+    # bf16-pair MFMAs in the mixed path (both FP64 in the FP64 path); the
+    # bound is the time both halves take at their peaks
+    half = fl / max(1, xc_launches) / 2.0
+    pk2 = PEAK["bf16"] if dtype == "f32" else PEAK["f64"]
+    t_bound = half / (PEAK[dtype] * 1e12) + half / (pk2 * 1e12)
+    per_dtype = dict(x_phi_p=dtype, phit_w="bf16 pairs" if dtype == "f32" else "f64",
+                     bound_ms=t_bound * 1e3, frac=t_bound / (xc_ms * 1e-3) if xc_launches else float("nan"))
+    scr = screened_ratio(args)
+    fls = xc_flops(info["nbf"], info["ngrid"], niter, ngridc, ncoarse, scr["main"], scr["coarse"]) if scr else None
     roof = dict(bound="mfma", kernel="xc_kernel", achieved=achieved, peak=PEAK[dtype], unit="TFLOP/s",
-                frac=achieved / PEAK[dtype], traffic=measured_traffic(args, "mixed" if dtype == "f32" else "fp64"),
+                frac=achieved / PEAK[dtype], per_dtype=per_dtype,
+                screened=(dict(flops_per_launch=fls / max(1, xc_launches), ratio=fls / fl,
+                               frac=achieved * (fls / fl) / PEAK[dtype], source=scr["source"]) if scr else None),
+                traffic=measured_traffic(args, "mixed" if dtype == "f32" else "fp64"),
                 flops_per_launch=fl / max(1, xc_launches), avg_launch_ms=xc_ms, launches=xc_launches)
 
     # work rates of the other kernels, from the same live HIP-event timings:
@@ -390,9 +533,13 @@ def main():
                      avg_launch_ms=grid_ms),
     }
 
+    legs_out = None
+    if legs:
+        legs_out = config_legs(ks, torch, water, c1, args)
+
     serving = None
     if args.serve_requests > 0:
-        serving = serving_leg(ks, args)
+        serving = serving_leg(ks, args, reqs)
         print("serving: %.1f solves/s saturated, lambda %.1f/s, p50 %.3f s p99 %.3f s"
               % (serving["saturated_solves_per_s"], serving["arrival_rate_per_s"], serving["p50_latency_s"],
                  serving["p99_latency_s"]), file=sys.stderr, flush=True)
@@ -429,7 +576,12 @@ def main():
                    "nbf_range": [min(info["nbf"]), max(info["nbf"])],
                    "grid_points": int(sum(info["ngrid"])),
                    "coarse_grid": args.coarse_grid,
-                   "precision": "mixed: ERI/JK/XC FP32, Loewdin/eigh/DIIS/energy FP64" if dtype == "f32" else "fp64"},
+                   "precision": ("mixed: ERIs evaluated and stored in FP32 (prefactors formed in FP64); J/K "
+                                 "digests FP32 integrals against the FP64 density with FP64 accumulation; XC in "
+                                 "FP32 (AO values, X = Phi P on FP32 MFMAs, functional) with Phi^T W on bf16 split "
+                                 "pairs (operands within 2^-17, FP32 accumulation) and E_xc summed in FP64; "
+                                 "Loewdin, eigensolve, DIIS, Fock and energy in FP64")
+                                if dtype == "f32" else "fp64"},
         "iterations": {"mean": float(np.mean(niter)), "max": int(max(niter)),
                        "coarse_grid_mean": float(np.mean(ncoarse))},
         "unconverged": int(sum(s != 1 for s in status)),
@@ -439,6 +591,7 @@ def main():
         "fp64": fp64,
         "accuracy": acc,
         "vs_oracle": vs_oracle,
+        "configs": legs_out,
         "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
