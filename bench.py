@@ -36,8 +36,14 @@ METRIC = "SCF solves/sec, 9–11 heavy atoms, FP32 vs FP64 (|ΔE|≤1e-4 Ha); p9
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # MI355X dense MFMA TFLOP/s (FP64, FP32, bf16)
 HBM_PEAK = 8000.0                      # GB/s
 SCREENING = os.path.join(ROOT, "tests", "golden", "xc_screening_seed2.json")
-TRAFFIC = os.path.join(ROOT, "profiles", "xc_kernel_traffic.json")
-XC_SOURCE = os.path.join(ROOT, "paper_2311_01135_amd", "csrc", "k_xc.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "counters_4096mol_9-11heavy_mixed.json")
+CSRC = os.path.join(ROOT, "paper_2311_01135_amd", "csrc")
+# kernel family -> (rocprofv3 kernel-name prefix, sources its code comes from)
+COUNTER_KERNELS = {
+    "xc": ("ks::xc_kernel<", ["k_xc.hip"]),
+    "jk": ("ks::jk_class_kernel<", ["k_jk.hip", "jk_scatter.h"]),
+    "eri": ("ks::eri_class_kernel<", ["k_ints.hip"]),
+}
 
 
 def parse():
@@ -65,6 +71,10 @@ def parse():
     p.add_argument("--schwarz-tol", type=float, default=0.0, help="Schwarz screening threshold (0 = off)")
     p.add_argument("--basis", choices=["sto-3g", "6-31g"], default="sto-3g",
                    help="6-31G covers H, C, N, O: molecules with F are replaced by F-free trees of the same size")
+    p.add_argument("--summarize-counters", default="",
+                   help="no GPU: summarise the rocprofv3 counter directories under this path into the committed "
+                        "profiles/ counter summary (workload from the other options)")
+    p.add_argument("--summarize-command", default="", help="the profiling command, recorded in the summary")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="run one plain streaming copy of this many MiB before the timed region (the reference "
                         "kernel that scales hardware byte counters)")
@@ -114,25 +124,108 @@ def xc_flops(nbf, ngrid, niter, ngridc=None, ncoarse=None, r_main=1.0, r_coarse=
                      for n, g, it, gc, ic in zip(nbf, ngrid, niter, ngridc, ncoarse)))
 
 
-def measured_traffic(args, prec_name):
-    """HBM bytes per XC launch from the committed counter summary, when it
-    was taken on this workload from the current kernel source; else None."""
+def _sha(files):
     import hashlib
-    if not os.path.exists(TRAFFIC):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def summarize_counters(d, out, workload):
+    """Counter summary of a profiled benchmark run (rocprofv3 output
+    directories under d: kt (kernel trace), pa/pb/pc (SQ counters), pf
+    (FETCH_SIZE), pw (WRITE_SIZE), written with -o <name> --output-format
+    csv): per kernel family its launches, average duration, HBM bytes per
+    launch (each counter scaled by what it reads for the copy-calibration
+    kernel), MFMA busy fraction, VALU floating-point operations and LDS
+    statistics, with the hash of the sources the counters were taken on."""
+    import csv
+    import collections
+
+    def rows(name):
+        with open(os.path.join(d, name, name + "_counter_collection.csv")) as f:
+            return list(csv.DictReader(f))
+
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    copy = {}
+    owner = {}                 # a counter collected in several passes is taken from the first
+    for pas in ("pa", "pb", "pc", "pf", "pw"):
+        for r in rows(pas):
+            k = r["Kernel_Name"]
+            name = r["Counter_Name"]
+            if owner.setdefault(name, pas) != pas:
+                continue
+            v = float(r["Counter_Value"])
+            if "vectorized_elementwise_kernel" in k and "MulFunctor" in k:
+                copy[name] = copy.get(name, 0.0) + v
+                continue
+            for fam, (prefix, _) in COUNTER_KERNELS.items():
+                if k.startswith(prefix) or k.startswith("void " + prefix):
+                    agg[fam][name] += v
+                    disp[(fam, pas)].add(r["Dispatch_Id"])
+    dur = collections.defaultdict(list)
+    with open(os.path.join(d, "kt", "kt_kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            for fam, (prefix, _) in COUNTER_KERNELS.items():
+                k = r["Kernel_Name"]
+                if k.startswith(prefix) or k.startswith("void " + prefix):
+                    dur[fam].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    mib = workload.get("copy_calibration_mib", 1024)
+    fetch_factor = mib * 1024.0 / copy["FETCH_SIZE"] if copy.get("FETCH_SIZE") else None
+    write_factor = mib * 1024.0 / copy["WRITE_SIZE"] if copy.get("WRITE_SIZE") else None
+    doc = dict(workload=workload, copy_calibration=dict(mib=mib, fetch_factor=fetch_factor, write_factor=write_factor),
+               kernels={})
+    for fam, (prefix, srcs) in COUNTER_KERNELS.items():
+        c = agg[fam]
+        n = len(disp[(fam, "pa")]) or 1
+        gui = c.get("GRBM_GUI_ACTIVE", 0.0) / 8.0           # summed over the 8 XCDs
+        ent = dict(kernel=prefix, sources=srcs, source_sha256=_sha(srcs), launches_pmc=n,
+                   launches_trace=len(dur[fam]), avg_ms_trace=(sum(dur[fam]) / len(dur[fam]) / 1e6) if dur[fam] else None)
+        if fetch_factor and "FETCH_SIZE" in c:
+            ent["hbm_bytes_per_launch"] = (c["FETCH_SIZE"] * fetch_factor + c.get("WRITE_SIZE", 0.0) * write_factor) \
+                * 1024.0 / max(1, len(disp[(fam, "pf")]))
+        if gui:
+            ent["mfma_busy_frac"] = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (gui * 1024.0)
+            ent["lds_busy_frac"] = c.get("SQ_LDS_IDX_ACTIVE", 0.0) / (gui * 256.0)
+            ent["lds_bank_conflict_frac"] = c.get("SQ_LDS_BANK_CONFLICT", 0.0) / (gui * 256.0)
+            ent["valu_issue_frac"] = 4.0 * c.get("SQ_INSTS_VALU", 0.0) / (gui * 1024.0)
+        fl32 = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F32", 0.0) + c.get("SQ_INSTS_VALU_MUL_F32", 0.0)
+                       + c.get("SQ_INSTS_VALU_ADD_F32", 0.0))
+        fl64 = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F64", 0.0) + c.get("SQ_INSTS_VALU_MUL_F64", 0.0)
+                       + c.get("SQ_INSTS_VALU_ADD_F64", 0.0))
+        npc = max(1, len(disp[(fam, "pc")]))
+        ent["valu_flops_per_launch"] = dict(f32=fl32 / npc, f64=fl64 / npc,
+                                            transcendental_lane_ops=64.0 * (c.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
+                                                                            + c.get("SQ_INSTS_VALU_TRANS_F64", 0.0)) / npc)
+        ent["mfma_flops_per_launch"] = 512.0 * (c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
+                                                + c.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0)
+                                                + c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)) / n
+        ent["counters_per_launch"] = {k: v / n for k, v in sorted(c.items())}
+        doc["kernels"][fam] = ent
+    with open(out, "w") as f:
+        json.dump(doc, f, indent=1)
+    return doc
+
+
+def counters_for(args, fam):
+    """The committed counter summary of a kernel family, when it was taken on
+    this workload and the kernel's current sources; else None."""
+    if not os.path.exists(COUNTERS):
         return None
-    with open(TRAFFIC) as f:
-        t = json.load(f)
-    with open(XC_SOURCE, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    w = t.get("workload", {})
-    if (t.get("source_sha256") != sha or w.get("n_mol") != args.n_mol or w.get("seed") != args.seed
-            or w.get("heavy") != args.heavy or w.get("precision") != prec_name
-            or w.get("coarse_grid", "0,0,0") != args.coarse_grid):
+    with open(COUNTERS) as f:
+        doc = json.load(f)
+    w = doc.get("workload", {})
+    if (w.get("n_mol") != args.n_mol or w.get("seed") != args.seed or w.get("heavy") != args.heavy
+            or w.get("coarse_grid") != args.coarse_grid or args.basis != "sto-3g" or args.direct
+            or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24) or args.fp64_only):
         return None
-    # the counters were taken on the default STO-3G, stored-integral, 50x12x24 workload
-    if args.basis != "sto-3g" or args.direct or args.schwarz_tol > 0 or grid_shape(args) != (50, 12, 24):
+    ent = doc.get("kernels", {}).get(fam)
+    if not ent or ent.get("source_sha256") != _sha(ent["sources"]):
         return None
-    return t["traffic_bytes_per_launch"]
+    return ent
 
 
 def screened_ratio(args):
@@ -423,6 +516,14 @@ def cpu_baseline(mols, args):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        doc = summarize_counters(args.summarize_counters, COUNTERS,
+                                 dict(n_mol=args.n_mol, seed=args.seed, heavy=args.heavy, precision="mixed",
+                                      coarse_grid=args.coarse_grid, copy_calibration_mib=args.copy_calibration_mib
+                                      or 1024, command=args.summarize_command))
+        print(json.dumps({k: {kk: v[kk] for kk in v if kk != "counters_per_launch"}
+                          for k, v in doc["kernels"].items()}, indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -505,7 +606,8 @@ def main():
                 frac=achieved / PEAK[dtype], per_dtype=per_dtype,
                 screened=(dict(flops_per_launch=fls / max(1, xc_launches), ratio=fls / fl,
                                frac=achieved * (fls / fl) / PEAK[dtype], source=scr["source"]) if scr else None),
-                traffic=measured_traffic(args, "mixed" if dtype == "f32" else "fp64"),
+                traffic=(counters_for(args, "xc") or {}).get("hbm_bytes_per_launch"),
+                mfma_busy_frac=(counters_for(args, "xc") or {}).get("mfma_busy_frac"),
                 flops_per_launch=fl / max(1, xc_launches), avg_launch_ms=xc_ms, launches=xc_launches)
 
     # work rates of the other kernels, from the same live HIP-event timings:
@@ -520,12 +622,29 @@ def main():
     jk_bytes = float(sum(e * es * it for e, it in zip(info["n_eri"], niter))) / max(1, jk_n)
     jk_gbs = jk_bytes / (jk_ms * 1e-3) / 1e9 if jk_n else float("nan")
     jkd_ms, jkd_n = kt.get("jk_direct", (float("nan"), 0))
+    # ERI VALU work from the committed counters (floating-point lane operations
+    # of the class kernels per build), against this run's build time; J/K HBM
+    # bytes and LDS statistics likewise
+    ce, cj = counters_for(args, "eri"), counters_for(args, "jk")
+    eri_fl = ((ce["valu_flops_per_launch"]["f32"] + ce["valu_flops_per_launch"]["f64"]) * ce["launches_pmc"]
+              if ce else None)
+    vpk = PEAK["f32"] if main_prec == ks.KS_MIXED else PEAK["f64"]
     rates = {
         "eri": dict(bound="valu", unique_shell_quartets_per_s=nq / (eri_ms * 1e-3),
                     primitive_quartets_per_s=nprim / (eri_ms * 1e-3),
-                    unique_integrals_per_s=float(sum(info["n_eri"])) / (eri_ms * 1e-3), avg_launch_ms=eri_ms),
+                    unique_integrals_per_s=float(sum(info["n_eri"])) / (eri_ms * 1e-3), avg_launch_ms=eri_ms,
+                    class_ms={c: kt[k][0] for c, k in (("ssss", "eri_ssss"), ("psss", "eri_psss"),
+                                                        ("psps", "eri_psps"), ("ppss", "eri_ppss"),
+                                                        ("ppps", "eri_ppps"), ("pppp", "eri_pppp")) if k in kt},
+                    flops_per_build=eri_fl, achieved_tflops=(eri_fl / (eri_ms * 1e-3) / 1e12) if eri_fl else None,
+                    peak_tflops=vpk, frac=(eri_fl / (eri_ms * 1e-3) / 1e12 / vpk) if eri_fl else None,
+                    note="flops: VALU floating-point lane operations counted by rocprofv3 (2 per FMA) in the "
+                         "class kernels, committed profile; time: this run's build, beside the grid kernel"),
         "jk": dict(bound="hbm", achieved=jk_gbs, peak=HBM_PEAK, unit="GB/s", frac=jk_gbs / HBM_PEAK,
-                   bytes_per_launch=jk_bytes, avg_launch_ms=jk_ms, launches=jk_n),
+                   bytes_per_launch=jk_bytes, avg_launch_ms=jk_ms, launches=jk_n,
+                   traffic=cj.get("hbm_bytes_per_launch") if cj else None,
+                   lds_busy_frac=cj.get("lds_busy_frac") if cj else None,
+                   lds_bank_conflict_frac=cj.get("lds_bank_conflict_frac") if cj else None),
         "jk_direct": dict(bound="valu", avg_launch_ms=jkd_ms, launches=jkd_n,
                           note="integral-direct: ERIs recomputed inside the digestion, nothing streamed") if jkd_n else None,
         "grid": dict(bound="valu", becke_pairs_per_s=float(sum(g * n * (n - 1) / 2 for g, n in
