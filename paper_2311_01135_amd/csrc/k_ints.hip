@@ -238,6 +238,21 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
     constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr double pi25 = 2.0 * 17.493418327624862;   // 2 pi^(5/2)
+    // FP32 evaluation with an ss ket (the (ss|ss), (ps|ss), (pp|ss) classes):
+    // the nine ket primitive pairs' centres, exponents and scaled weights are
+    // read once into registers instead of once per bra primitive pair
+    constexpr bool kKetReg = (LC + LD == 0) && PP == kNPrimPair;
+    double kPr[kKetReg ? PP : 1][3];
+    R kqr[kKetReg ? PP : 1], kKr[kKetReg ? PP : 1];
+    if constexpr (kKetReg) {
+#pragma unroll
+        for (int jp = 0; jp < PP; jp++) {
+#pragma unroll
+            for (int d = 0; d < 3; d++) kPr[jp][d] = vk.get(1 + d, jp);
+            kqr[jp] = R(vk.get(0, jp));
+            kKr[jp] = R(vk.get(4, jp) * vk.get(5, jp));
+        }
+    }
 #pragma unroll
     for (int i = 0; i < NA * NB * NC * ND; i++) acc[i] = Acc(0);
     auto bra = [&](int ip) {
@@ -251,9 +266,20 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
 #pragma unroll
         for (int d = 0; d < 3; d++) hermite_E<R>(R(bP[d] - sa.A[d]), R(bP[d] - sb.A[d]), i2p, eb[d]);
         auto ket = [&](int jp) {
-            const double kP[3] = {vk.get(1, jp), vk.get(2, jp), vk.get(3, jp)};
-            const double iqd = vk.get(5, jp);
-            const R q = R(vk.get(0, jp)), Kkq = R(vk.get(4, jp) * iqd), iqv = R(iqd);
+            double kP[3];
+            R q, Kkq, iqv;
+            if constexpr (kKetReg) {
+                kP[0] = kPr[jp][0]; kP[1] = kPr[jp][1]; kP[2] = kPr[jp][2];
+                q = kqr[jp];
+                Kkq = kKr[jp];
+                iqv = R(1);                                // unused: an ss ket's Hermite expansion is 1
+            } else {
+                kP[0] = vk.get(1, jp); kP[1] = vk.get(2, jp); kP[2] = vk.get(3, jp);
+                const double iqd = vk.get(5, jp);
+                q = R(vk.get(0, jp));
+                Kkq = R(vk.get(4, jp) * iqd);
+                iqv = R(iqd);
+            }
             const R rs = rsqrt_nr(p + q);                 // 1/sqrt(p + q)
             const R pref = Kbp * Kkq * rs;
             if (fabs(pref) < cut) return;
@@ -334,7 +360,10 @@ __device__ __forceinline__ void eri_quartet(const Shell& sa, const Shell& sb, co
         // nine pairs' data in registers and drop to two or three waves per
         // SIMD, 467 -> 385 ms for the ERIs of 2048 molecules; the autotuner
         // picks per class); 6-31G: the real pairs in a plain loop
-        if constexpr (PP <= kNPrimPair) {
+        if constexpr (kKetReg) {
+#pragma unroll
+            for (int jp = 0; jp < PP; jp++) ket(jp);
+        } else if constexpr (PP <= kNPrimPair) {
             static_assert(PP % UNR == 0, "ket groups");
 #pragma unroll 1
             for (int j0 = 0; j0 < PP; j0 += UNR) {
