@@ -9,6 +9,12 @@
 namespace ks {
 
 constexpr int kScfThreads = 256;
+// Work groups whose matrices sit in LDS (one molecule per group, which fills
+// most of a CU's LDS: the eigensolver, and the DIIS, Loewdin, density and
+// guess products) run 16 wavefronts: their steps are latency-bound loops
+// between barriers, and more waves shorten each loop.
+constexpr int kEighThreads = 1024;
+constexpr int kScfThreadsFull = 1024;
 
 __device__ __forceinline__ void two_sum_add(double& s, double& c, double x)
 {
@@ -283,9 +289,9 @@ __device__ int diis_solve_dev(int n, const double* B, double* c)
 // error vector e = X^T (F P S - S P F) X, convergence test, DIIS push and
 // extrapolation, and F' = X^T Fbar X.
 template <bool FULL>
-__global__ __launch_bounds__(kScfThreads) void diis_kernel(ScfArgs g)
+__global__ __launch_bounds__(FULL ? kScfThreadsFull : kScfThreads) void diis_kernel(ScfArgs g)
 {
-    __shared__ double red[2 * kScfThreads / 64];
+    __shared__ double red[2 * kScfThreadsFull / 64];
     __shared__ double coef[kMaxDiis + 1];
     __shared__ int sl[kMaxDiis];
     __shared__ int nkeep;
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(kScfThreads) void atom_guess_kernel(const MolDesc* 
 
 // W = X^T A X (guess from the core Hamiltonian)
 template <bool FULL>
-__global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const double* __restrict__ A)
+__global__ __launch_bounds__(FULL ? kScfThreadsFull : kScfThreads) void xtax_kernel(ScfArgs g, const double* __restrict__ A)
 {
     const int m = blockIdx.x;
     const MolDesc md = g.mol[m];
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(kScfThreads) void xtax_kernel(ScfArgs g, const doub
 // diagonal close to self-consistency, so few sweeps remain; the sorted
 // vectors are kept in `keep` for the next iteration.  tmp: N^2 scratch.
 template <bool GLOBAL>
-__global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __restrict__ mols,
+__global__ __launch_bounds__(GLOBAL ? kScfThreads : kEighThreads) void eigh_kernel(const MolDesc* __restrict__ mols,
                                                            const MolState* __restrict__ state, int only_active,
                                                            const double* __restrict__ src, double* __restrict__ vecs,
                                                            double* __restrict__ vals, const double* __restrict__ warm,
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
     double* Vv = GLOBAL ? gws + 2 * nmat + md.mat0 : A + NN;
     __shared__ int rp[kMaxNbf / 2 + 1], rq[kMaxNbf / 2 + 1];
     __shared__ double rc[kMaxNbf / 2 + 1], rs[kMaxNbf / 2 + 1];
-    __shared__ double red[2 * kScfThreads / 64];
+    __shared__ double red[2 * kEighThreads / 64];
     __shared__ int rank_of[kMaxNbf];
     const double* a0 = src + md.mat0;
     const bool use_warm = warm && have_warm[m];
@@ -585,7 +591,7 @@ __global__ __launch_bounds__(kScfThreads) void eigh_kernel(const MolDesc* __rest
 // X = U s^-1/2 U^T from eigh(S) (vectors in C, values in eps); flags near-singular S.
 // The scaled vectors W = U s^-1/2 go to work, then X = W U^T.
 template <bool FULL>
-__global__ __launch_bounds__(kScfThreads) void lowdin_kernel(ScfArgs g)
+__global__ __launch_bounds__(FULL ? kScfThreadsFull : kScfThreads) void lowdin_kernel(ScfArgs g)
 {
     const int m = blockIdx.x;
     const MolDesc md = g.mol[m];
@@ -602,7 +608,7 @@ __global__ __launch_bounds__(kScfThreads) void lowdin_kernel(ScfArgs g)
 // C = X C'; unless this was the final iteration, P = 2 C_occ C_occ^T.
 // Final iterations keep P (the density that produced the last F) and retire.
 template <bool FULL>
-__global__ __launch_bounds__(kScfThreads) void density_kernel(ScfArgs g, int guess)
+__global__ __launch_bounds__(FULL ? kScfThreadsFull : kScfThreads) void density_kernel(ScfArgs g, int guess)
 {
     const int m = blockIdx.x;
     MolState& st = g.state[m];
@@ -712,7 +718,7 @@ static ks_status launch_mm(ks_batch* b, K1 kfull, K0 kpanel, Args... args)
     const size_t lds = matmul_lds(b);
     KS_HIP(hipFuncSetAttribute(full ? (const void*)kfull : (const void*)kpanel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    if (full) hipLaunchKernelGGL(kfull, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, args...);
+    if (full) hipLaunchKernelGGL(kfull, dim3(b->n_mol), dim3(kScfThreadsFull), lds, b->stream, args...);
     else hipLaunchKernelGGL(kpanel, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, args...);
     KS_HIP(hipGetLastError());
     return KS_OK;
@@ -727,7 +733,7 @@ static ks_status run_eigh(ks_batch* b, bool only_active, const double* src, doub
     const void* fn = eigh_fits(b) ? (const void*)eigh_kernel<false> : (const void*)eigh_kernel<true>;
     KS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (eigh_fits(b))
-        hipLaunchKernelGGL(eigh_kernel<false>, dim3(b->n_mol), dim3(kScfThreads), lds, b->stream, b->d_mol,
+        hipLaunchKernelGGL(eigh_kernel<false>, dim3(b->n_mol), dim3(kEighThreads), lds, b->stream, b->d_mol,
                            b->d_state, (int)only_active, src, vecs, vals, (const double*)warm, warm,
                            warm ? b->d_work : nullptr, warm ? b->d_have_warm : nullptr, nullptr, b->nmat);
     else
