@@ -178,11 +178,15 @@ def summarize_counters(d, out, workload):
     write_factor = mib * 1024.0 / copy["WRITE_SIZE"] if copy.get("WRITE_SIZE") else None
     doc = dict(workload=workload, copy_calibration=dict(mib=mib, fetch_factor=fetch_factor, write_factor=write_factor),
                kernels={})
+    n_iter = len(disp[("xc", "pa")]) or 1      # one XC launch per SCF iteration
     for fam, (prefix, srcs) in COUNTER_KERNELS.items():
         c = agg[fam]
         n = len(disp[(fam, "pa")]) or 1
         gui = c.get("GRBM_GUI_ACTIVE", 0.0) / 8.0           # summed over the 8 XCDs
-        ent = dict(kernel=prefix, sources=srcs, source_sha256=_sha(srcs), launches_pmc=n,
+        # launches per build: J/K runs two class-group kernels per iteration,
+        # the ERIs six class kernels once
+        per_build = n / n_iter if fam == "jk" else (n if fam == "eri" else 1)
+        ent = dict(kernel=prefix, sources=srcs, source_sha256=_sha(srcs), launches_pmc=n, launches_per_build=per_build,
                    launches_trace=len(dur[fam]), avg_ms_trace=(sum(dur[fam]) / len(dur[fam]) / 1e6) if dur[fam] else None)
         if fetch_factor and "FETCH_SIZE" in c:
             ent["hbm_bytes_per_launch"] = (c["FETCH_SIZE"] * fetch_factor + c.get("WRITE_SIZE", 0.0) * write_factor) \
@@ -626,7 +630,7 @@ def main():
     # of the class kernels per build), against this run's build time; J/K HBM
     # bytes and LDS statistics likewise
     ce, cj = counters_for(args, "eri"), counters_for(args, "jk")
-    eri_fl = ((ce["valu_flops_per_launch"]["f32"] + ce["valu_flops_per_launch"]["f64"]) * ce["launches_pmc"]
+    eri_fl = ((ce["valu_flops_per_launch"]["f32"] + ce["valu_flops_per_launch"]["f64"]) * ce["launches_per_build"]
               if ce else None)
     vpk = PEAK["f32"] if main_prec == ks.KS_MIXED else PEAK["f64"]
     rates = {
@@ -642,7 +646,8 @@ def main():
                          "class kernels, committed profile; time: this run's build, beside the grid kernel"),
         "jk": dict(bound="hbm", achieved=jk_gbs, peak=HBM_PEAK, unit="GB/s", frac=jk_gbs / HBM_PEAK,
                    bytes_per_launch=jk_bytes, avg_launch_ms=jk_ms, launches=jk_n,
-                   traffic=cj.get("hbm_bytes_per_launch") if cj else None,
+                   traffic=(cj["hbm_bytes_per_launch"] * cj["launches_per_build"]
+                            if cj and "hbm_bytes_per_launch" in cj else None),
                    lds_busy_frac=cj.get("lds_busy_frac") if cj else None,
                    lds_bank_conflict_frac=cj.get("lds_bank_conflict_frac") if cj else None),
         "jk_direct": dict(bound="valu", avg_launch_ms=jkd_ms, launches=jkd_n,
