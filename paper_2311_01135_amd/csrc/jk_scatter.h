@@ -8,6 +8,7 @@
 #pragma once
 
 #include "ks_internal.h"
+#include "wave.h"
 
 namespace ks {
 
@@ -24,12 +25,17 @@ template <int NA, int NB, int NC, int ND, typename A, typename SI = A>
 __device__ __forceinline__ void jk_scatter(const SI (&I)[NA * NB * NC * ND], int oa, int ob, int oc, int od, A f,
                                            int bra_key, int N, const A* __restrict__ Ps, A* AJ, A* AK)
 {
-    const int i = bra_key;
-    A pab[NA][NB], pcd[NC][ND], pbd[NB][ND], pbc[NB][NC], pad[NA][ND], pac[NA][NC];
-#pragma unroll
-    for (int a = 0; a < NA; a++)
-#pragma unroll
-        for (int b = 0; b < NB; b++) pab[a][b] = Ps[(oa + a) * N + ob + b];
+    const A f2 = A(2) * f;
+    // J_ab: the lanes of a wave usually share the bra pair; then the wave
+    // sums its contributions and one lane adds them (same-address LDS
+    // atomics would serialise)
+    const unsigned long long act = __ballot(1);
+    const unsigned long long same = __ballot(__builtin_amdgcn_readfirstlane(bra_key) == bra_key);
+    const bool wave_bra = act == ~0ull && same == act;
+    // density blocks and accumulators that involve no bra function a, kept
+    // over the loop on a; the a-dependent ones are formed and flushed per a,
+    // which bounds the live registers of the large classes
+    A pcd[NC][ND], pbd[NB][ND], pbc[NB][NC];
 #pragma unroll
     for (int c = 0; c < NC; c++)
 #pragma unroll
@@ -41,16 +47,17 @@ __device__ __forceinline__ void jk_scatter(const SI (&I)[NA * NB * NC * ND], int
 #pragma unroll
         for (int c = 0; c < NC; c++) pbc[b][c] = Ps[(ob + b) * N + oc + c];
     }
+    A jcd[NC][ND] = {}, kbc[NB][NC] = {}, kbd[NB][ND] = {};
 #pragma unroll
     for (int a = 0; a < NA; a++) {
+        A pab[NB], pad[ND], pac[NC];
 #pragma unroll
-        for (int d = 0; d < ND; d++) pad[a][d] = Ps[(oa + a) * N + od + d];
+        for (int b = 0; b < NB; b++) pab[b] = Ps[(oa + a) * N + ob + b];
 #pragma unroll
-        for (int c = 0; c < NC; c++) pac[a][c] = Ps[(oa + a) * N + oc + c];
-    }
-    A jab[NA][NB] = {}, jcd[NC][ND] = {}, kac[NA][NC] = {}, kbc[NB][NC] = {}, kad[NA][ND] = {}, kbd[NB][ND] = {};
+        for (int d = 0; d < ND; d++) pad[d] = Ps[(oa + a) * N + od + d];
 #pragma unroll
-    for (int a = 0; a < NA; a++)
+        for (int c = 0; c < NC; c++) pac[c] = Ps[(oa + a) * N + oc + c];
+        A jab[NB] = {}, kac[NC] = {}, kad[ND] = {};
 #pragma unroll
         for (int b = 0; b < NB; b++)
 #pragma unroll
@@ -58,46 +65,32 @@ __device__ __forceinline__ void jk_scatter(const SI (&I)[NA * NB * NC * ND], int
 #pragma unroll
                 for (int d = 0; d < ND; d++) {
                     const A v = A(I[((a * NB + b) * NC + c) * ND + d]);
-                    jab[a][b] += v * pcd[c][d];
-                    jcd[c][d] += v * pab[a][b];
-                    kac[a][c] += v * pbd[b][d];
-                    kbc[b][c] += v * pad[a][d];
-                    kad[a][d] += v * pbc[b][c];
-                    kbd[b][d] += v * pac[a][c];
+                    jab[b] += v * pcd[c][d];
+                    jcd[c][d] += v * pab[b];
+                    kac[c] += v * pbd[b][d];
+                    kbc[b][c] += v * pad[d];
+                    kad[d] += v * pbc[b][c];
+                    kbd[b][d] += v * pac[c];
                 }
-    const A f2 = A(2) * f;
-    // J_ab: the lanes of a wave usually share the bra pair; then the wave
-    // sums its contributions and one lane adds them (same-address LDS
-    // atomics would serialise)
-    const unsigned long long act = __ballot(1);
-    const unsigned long long same = __ballot(__builtin_amdgcn_readfirstlane(i) == i);
-    if (act == ~0ull && same == act) {
-#pragma unroll
-        for (int a = 0; a < NA; a++)
+        if (wave_bra) {
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                A v = f2 * jab[a][b];
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                const A v = wave_sum(f2 * jab[b]);
                 if ((threadIdx.x & 63) == 0) lds_add(&AJ[(oa + a) * N + ob + b], v);
             }
-    } else {
+        } else {
 #pragma unroll
-        for (int a = 0; a < NA; a++)
+            for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[b]);
+        }
 #pragma unroll
-            for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[a][b]);
+        for (int c = 0; c < NC; c++) lds_add(&AK[(oa + a) * N + oc + c], f * kac[c]);
+#pragma unroll
+        for (int d = 0; d < ND; d++) lds_add(&AK[(oa + a) * N + od + d], f * kad[d]);
     }
 #pragma unroll
     for (int c = 0; c < NC; c++)
 #pragma unroll
         for (int d = 0; d < ND; d++) lds_add(&AJ[(oc + c) * N + od + d], f2 * jcd[c][d]);
-#pragma unroll
-    for (int a = 0; a < NA; a++) {
-#pragma unroll
-        for (int c = 0; c < NC; c++) lds_add(&AK[(oa + a) * N + oc + c], f * kac[a][c]);
-#pragma unroll
-        for (int d = 0; d < ND; d++) lds_add(&AK[(oa + a) * N + od + d], f * kad[a][d]);
-    }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
 #pragma unroll

@@ -851,9 +851,7 @@ __device__ __forceinline__ void direct_class_rows(const DirectArgs& g, const Mol
         for (int a = 0; a < NA; a++)
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                double v = jab[a][b];
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                const double v = wave_sum(jab[a][b]);
                 if ((threadIdx.x & 63) == 0 && v != 0.0) lds_add(&AJ[(oa + a) * N + ob + b], v);
             }
         __syncthreads();

@@ -57,14 +57,14 @@ struct JkArgs {
 constexpr int kJkThreads = 512;
 
 
+// Ps, AJ, AK: N x N matrices in LDS with row stride ld.
 template <int LA, int LB, int LC, int LD, typename S, typename A>
 __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md, int chunk, int nchunk,
-                                             const A* __restrict__ Ps, A* AJ, A* AK)
+                                             const A* __restrict__ Ps, A* AJ, A* AK, int ld)
 {
     constexpr int C = (LA + LB == 0) ? 0 : (LA + LB == 1 ? (LC + LD == 0 ? 1 : 2) : (LC + LD == 0 ? 3 : (LC + LD == 1 ? 4 : 5)));
     constexpr int NA = LA ? 3 : 1, NB = LB ? 3 : 1, NC = LC ? 3 : 1, ND = LD ? 3 : 1;
     constexpr int NCOMP = NA * NB * NC * ND;
-    const int N = md.nbf;
     const long nq = md.nq[C];
     const long lo = nq * chunk / nchunk, hi = nq * (chunk + 1) / nchunk;
     const S* __restrict__ eri = (const S*)g.eri[C];
@@ -73,50 +73,77 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
     const int2* __restrict__ pk = g.pao[class_ket(C)] + md.pair0[class_ket(C)];
     const int nket = md.npair[class_ket(C)];
     const int step = blockDim.x;
-    int i = 0, j = 0;
-    // the integrals of the thread's next quartet are loaded one iteration
-    // ahead (classes of up to 27 components), so their HBM latency overlaps
-    // the current quartet's scatter; they stay in the storage type until use
+    // Each lane takes U of its quartets (q, q + step, ...) per batch and
+    // loads their integrals together, and (classes of up to 27 components)
+    // issues the next batch's loads before this batch's scatter: with one
+    // work group per CU, one quartet in flight per lane leaves the HBM stream
+    // latency-bound.  The integrals stay in the storage type until use.
+    constexpr int U = sizeof(S) == 4 ? (NCOMP <= 3 ? 4 : NCOMP <= 9 ? 2 : 1)
+                                     : (NCOMP == 1 ? 4 : NCOMP <= 3 ? 2 : 1);
     constexpr bool kAhead = NCOMP <= 27;
-    S cur[NCOMP];
-    if (lo + threadIdx.x < hi) {
-        decode_quartet_jk(C, lo + threadIdx.x, nket, i, j);
-        if constexpr (kAhead) {
-#pragma unroll
-            for (int k = 0; k < NCOMP; k++) cur[k] = eri[(size_t)k * NQ + md.q0[C] + lo + threadIdx.x];
-        }
-    }
-    for (long q = lo + threadIdx.x; q < hi; q += step) {
-        const int2 P1 = pb[i], P2 = pk[j];
-        const int oa = P1.x & 0xffff, ob = P1.y, oc = P2.x & 0xffff, od = P2.y;
-        A f = A(1);
-        if (P1.x >> 16) f *= A(0.5);
-        if (P2.x >> 16) f *= A(0.5);
-        if (class_tri(C) && i == j) f *= A(0.5);
-        // the next quartet of this thread: (i, j) advanced by step in row-major
-        // order over the triangle (j <= i) or the rectangle (j < nket)
-        int i2 = i, j2 = j + step;
+    const long ustep = (long)U * step;
+    const size_t qoff = md.q0[C];
+    // (i, j) of the lane's quartet advanced by step in row-major order over
+    // the triangle (j <= i) or the rectangle (j < nket)
+    auto advance = [&](int& i2, int& j2) {
+        j2 += step;
         if (class_tri(C)) {
             while (j2 > i2) { j2 -= i2 + 1; i2++; }
         } else {
             while (j2 >= nket) { j2 -= nket; i2++; }
         }
-        S I[NCOMP];
+    };
+    auto load = [&](long qb, S (&dst)[U][NCOMP]) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const long qu = qb + (long)u * step;
+            if (qu < hi) {
+#pragma unroll
+                for (int k = 0; k < NCOMP; k++) dst[u][k] = eri[(size_t)k * NQ + qoff + qu];
+            }
+        }
+    };
+    long q = lo + threadIdx.x;
+    if (q >= hi) return;
+    int ci, cj;
+    decode_quartet_jk(C, q, nket, ci, cj);
+    S cur[U][NCOMP];
+    if constexpr (kAhead) load(q, cur);
+    for (; q < hi; q += ustep) {
+        S I[U][NCOMP];
         if constexpr (kAhead) {
 #pragma unroll
-            for (int k = 0; k < NCOMP; k++) I[k] = cur[k];
-            if (q + step < hi) {
-                const long qn = md.q0[C] + q + step;
+            for (int u = 0; u < U; u++)
 #pragma unroll
-                for (int k = 0; k < NCOMP; k++) cur[k] = eri[(size_t)k * NQ + qn];
-            }
+                for (int k = 0; k < NCOMP; k++) I[u][k] = cur[u][k];
+            load(q + ustep, cur);
         } else {
-#pragma unroll
-            for (int k = 0; k < NCOMP; k++) I[k] = eri[(size_t)k * NQ + md.q0[C] + q];
+            load(q, I);
         }
-        jk_scatter<NA, NB, NC, ND, A, S>(I, oa, ob, oc, od, f, i, N, Ps, AJ, AK);
-        i = i2;
-        j = j2;
+        // the batch's pair-table entries, all loaded before the first scatter
+        int bi[U], bj[U];
+        int2 P1[U], P2[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            bi[u] = ci;
+            bj[u] = cj;
+            if (q + (long)u * step < hi) {
+                P1[u] = pb[ci];
+                P2[u] = pk[cj];
+            }
+            advance(ci, cj);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (q + (long)u * step < hi) {
+                A f = A(1);
+                if (P1[u].x >> 16) f *= A(0.5);
+                if (P2[u].x >> 16) f *= A(0.5);
+                if (class_tri(C) && bi[u] == bj[u]) f *= A(0.5);
+                jk_scatter<NA, NB, NC, ND, A, S>(I[u], P1[u].x & 0xffff, P1[u].y, P2[u].x & 0xffff, P2[u].y, f, bi[u],
+                                                 ld, Ps, AJ, AK);
+            }
+        }
     }
 }
 
@@ -184,9 +211,7 @@ __device__ __forceinline__ void digest_class_rows(const JkArgs& g, const MolDesc
         for (int a = 0; a < NA; a++)
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                double v = jab[a][b];
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                const double v = wave_sum(jab[a][b]);
                 if ((threadIdx.x & 63) == 0 && v != 0.0) lds_add(&AJ[(oa + a) * N + ob + b], v);
             }
         __syncthreads();
@@ -238,36 +263,44 @@ __global__ __launch_bounds__(kJkThreads) void jk_kernel(JkArgs g)
 // wavefronts of the (pp|pp)-bearing group.  The first group of a build
 // starts its partial J/K from zero, the later ones from the partial the
 // earlier groups wrote for the same work item.
+// LDS row stride of the N x N matrices: even, so that lanes whose ket pairs
+// step along an anti-diagonal (c + 1, d - 1) address rows ld - 1 (odd)
+// elements apart and fall in distinct banks (with ld = N odd, the stride N - 1
+// is even and up to 32 lanes share a bank in the P_cd reads and J_cd atomics).
+__host__ __device__ constexpr int jk_ld(int n) { return n + (n & 1); }
+
 template <typename S, typename A, int CMASK, int NTH, bool FIRST>
 __global__ __launch_bounds__(NTH) void jk_class_kernel(JkArgs g)
 {
     const JkItem it = g.items[blockIdx.x];
     if (g.only_active && g.state[it.mol].status != KS_MOL_ACTIVE) return;
     const MolDesc md = g.mol[it.mol];
-    const int N = md.nbf, NN = N * N;
+    const int N = md.nbf, NN = N * N, ld = jk_ld(N), NL = N * ld;
     extern __shared__ __align__(16) unsigned char smem_jk[];
     A* Pl = (A*)smem_jk;
-    A* AJ = Pl + NN;
-    A* AK = AJ + NN;
+    A* AJ = Pl + NL;
+    A* AK = AJ + NL;
     const double* P = g.P + md.mat0;
     const double* Pr = g.Pref ? g.Pref + md.mat0 : nullptr;
     A* out = (A*)g.part + (size_t)blockIdx.x * 2 * g.part_stride;
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-        Pl[i] = A(Pr ? P[i] - Pr[i] : P[i]);
-        AJ[i] = FIRST ? A(0) : out[i];
-        AK[i] = FIRST ? A(0) : out[g.part_stride + i];
+        const int l = (i / N) * ld + i % N;
+        Pl[l] = A(Pr ? P[i] - Pr[i] : P[i]);
+        AJ[l] = FIRST ? A(0) : out[i];
+        AK[l] = FIRST ? A(0) : out[g.part_stride + i];
     }
     __syncthreads();
-    if constexpr ((CMASK & 1) != 0) digest_class<0, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
-    if constexpr ((CMASK & 2) != 0) digest_class<1, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
-    if constexpr ((CMASK & 4) != 0) digest_class<1, 0, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
-    if constexpr ((CMASK & 8) != 0) digest_class<1, 1, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
-    if constexpr ((CMASK & 16) != 0) digest_class<1, 1, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
-    if constexpr ((CMASK & 32) != 0) digest_class<1, 1, 1, 1, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK);
+    if constexpr ((CMASK & 1) != 0) digest_class<0, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK, ld);
+    if constexpr ((CMASK & 2) != 0) digest_class<1, 0, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK, ld);
+    if constexpr ((CMASK & 4) != 0) digest_class<1, 0, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK, ld);
+    if constexpr ((CMASK & 8) != 0) digest_class<1, 1, 0, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK, ld);
+    if constexpr ((CMASK & 16) != 0) digest_class<1, 1, 1, 0, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK, ld);
+    if constexpr ((CMASK & 32) != 0) digest_class<1, 1, 1, 1, S, A>(g, md, it.chunk, it.nchunk, Pl, AJ, AK, ld);
     __syncthreads();
     for (int i = threadIdx.x; i < NN; i += blockDim.x) {
-        out[i] = AJ[i];
-        out[g.part_stride + i] = AK[i];
+        const int l = (i / N) * ld + i % N;
+        out[i] = AJ[l];
+        out[g.part_stride + i] = AK[l];
     }
 }
 
@@ -321,7 +354,8 @@ __global__ void jk_reduce_kernel(const MolDesc* __restrict__ mols, const MolStat
     if (Pnext) Pref[md.mat0 + t] = Pnext[md.mat0 + t];
 }
 
-// LDS accumulation type: FP64 whenever 3 N^2 doubles fit the 160 KB LDS.
+// LDS accumulation type: FP64 whenever 3 N^2 doubles (rows padded to an even
+// stride) fit the 160 KB LDS.
 // The digest is bound by its LDS atomics, and on gfx950 ds_add_f64 runs at
 // twice the rate of ds_add_f32 here, so the mixed path stores its ERIs in
 // FP32 (half the HBM stream) but accumulates J/K in FP64; molecules above 82
@@ -332,7 +366,7 @@ int jk_mode(const ks_batch* b)
 {
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
-    const size_t nn3 = 3 * (size_t)maxn * maxn;
+    const size_t nn3 = 3 * (size_t)maxn * jk_ld(maxn);
     if (nn3 * sizeof(double) <= 163840) return 0;
     if (b->opt.prec == KS_MIXED && nn3 * sizeof(float) <= 163840) return 1;
     return 2;
@@ -346,7 +380,7 @@ size_t jk_lds_bytes(const ks_batch* b)
     int maxn = 0;
     for (auto& m : b->mol) maxn = std::max(maxn, m.nbf);
     if (mode == 2) return 12 * (size_t)maxn * sizeof(double);   // density and K rows of one bra
-    return 3 * (size_t)maxn * maxn * (mode == 0 ? sizeof(double) : sizeof(float));
+    return 3 * (size_t)maxn * jk_ld(maxn) * (mode == 0 ? sizeof(double) : sizeof(float));
 }
 
 ks_status launch_delta(ks_batch* b, const double* P, const double* Pref, bool only_active)

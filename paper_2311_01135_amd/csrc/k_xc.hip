@@ -18,6 +18,7 @@
 // over the whole chunk.  V_XC = sum_chunks (A + A^T) is summed in FP64
 // afterwards.
 #include "kernels.h"
+#include "wave.h"
 
 namespace ks {
 
@@ -457,46 +458,6 @@ __device__ __forceinline__ f4_t mfma_pair(u32x4_t a, u32x4_t b, f4_t c)
 // q = lane / 16 supplies k = 4 q + j to the j-th of four MFMAs, so a lane's
 // four values along k are contiguous in LDS (one vector read) whenever the
 // operand is stored k-contiguous.
-
-// Sum over the four rows of 16 lanes, left in every lane: the gfx950
-// permlane swaps (v_permlane16_swap / v_permlane32_swap, VALU, no LDS
-// traffic) exchange odd and even rows, then the two halves of the wave; with
-// both operands the same value the two results add to x + x(lane ^ 16),
-// then to the sum over lane ^ 32.  FP64 values travel as two 32-bit halves.
-__device__ __forceinline__ float sum_rows(float x)
-{
-    const unsigned int u = __builtin_bit_cast(unsigned int, x);
-    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    x = __builtin_bit_cast(float, (unsigned int)a[0]) + __builtin_bit_cast(float, (unsigned int)a[1]);
-    const unsigned int v = __builtin_bit_cast(unsigned int, x);
-    const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return __builtin_bit_cast(float, (unsigned int)b[0]) + __builtin_bit_cast(float, (unsigned int)b[1]);
-}
-__device__ __forceinline__ double swap_rows(double x, bool wide, double& other)
-{
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-    const unsigned int lo = (unsigned int)u, hi = (unsigned int)(u >> 32);
-    unsigned int a0, a1, b0, b1;
-    if (wide) {
-        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        a0 = l[0]; a1 = l[1]; b0 = h[0]; b1 = h[1];
-    } else {
-        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        a0 = l[0]; a1 = l[1]; b0 = h[0]; b1 = h[1];
-    }
-    other = __builtin_bit_cast(double, (unsigned long long)a1 | ((unsigned long long)b1 << 32));
-    return __builtin_bit_cast(double, (unsigned long long)a0 | ((unsigned long long)b0 << 32));
-}
-__device__ __forceinline__ double sum_rows(double x)
-{
-    double o;
-    double s = swap_rows(x, false, o);
-    x = s + o;
-    s = swap_rows(x, true, o);
-    return s + o;
-}
 
 // X^T tiles (t = wave + NW j, j < NJ; AO tile t / (BP/16), point tile
 // t % (BP/16)) of X^T = P Phi^T over K = NP, then, from the tile in
