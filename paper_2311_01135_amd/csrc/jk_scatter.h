@@ -21,17 +21,23 @@ __device__ __forceinline__ void lds_add(A* p, A v)
 // I: the quartet's NA NB NC ND components (a slowest); oa..od: first AO of
 // each shell; bra_key: identifies the bra pair (lanes of a wavefront that
 // all share it sum their J_ab contributions before a single LDS atomic).
-template <int NA, int NB, int NC, int ND, typename A, typename SI = A>
+// FULL: every lane of the wavefront calls (lanes without a quartet pass
+// valid = false, zero integrals and in-range AO offsets); lanes that share a
+// bra pair then sum their J_ab contributions over the wavefront whatever
+// the number of bra pairs in it.  Otherwise (callers in divergent code)
+// only a wavefront whose lanes all share one bra pair sums them, and the
+// rest add per lane.  FP64 LDS atomics to one address from many lanes of
+// an instruction serialise (about 0.3 lane-updates per cycle per CU
+// against about 7 at distinct banks).
+template <int NA, int NB, int NC, int ND, typename A, typename SI = A, bool FULL = false>
 __device__ __forceinline__ void jk_scatter(const SI (&I)[NA * NB * NC * ND], int oa, int ob, int oc, int od, A f,
-                                           int bra_key, int N, const A* __restrict__ Ps, A* AJ, A* AK)
+                                           int bra_key, int N, const A* __restrict__ Ps, A* AJ, A* AK,
+                                           bool valid = true)
 {
     const A f2 = A(2) * f;
-    // J_ab: the lanes of a wave usually share the bra pair; then the wave
-    // sums its contributions and one lane adds them (same-address LDS
-    // atomics would serialise)
-    const unsigned long long act = __ballot(1);
-    const unsigned long long same = __ballot(__builtin_amdgcn_readfirstlane(bra_key) == bra_key);
-    const bool wave_bra = act == ~0ull && same == act;
+    const unsigned long long act = __ballot(valid);
+    const unsigned long long same = __ballot(valid && __builtin_amdgcn_readfirstlane(bra_key) == bra_key);
+    const bool wave_bra = FULL ? same == ~0ull : (act == ~0ull && same == act);
     // density blocks and accumulators that involve no bra function a, kept
     // over the loop on a; the a-dependent ones are formed and flushed per a,
     // which bounds the live registers of the large classes
@@ -78,25 +84,45 @@ __device__ __forceinline__ void jk_scatter(const SI (&I)[NA * NB * NC * ND], int
                 const A v = wave_sum(f2 * jab[b]);
                 if ((threadIdx.x & 63) == 0) lds_add(&AJ[(oa + a) * N + ob + b], v);
             }
+        } else if (FULL) {
+            // one wavefront sum per bra pair present (the lanes' bra pairs
+            // are few and contiguous); the loop bound is wavefront-uniform
+            unsigned long long rem = act;
+            while (rem) {
+                const int leader = __builtin_ctzll(rem);
+                const int key = __builtin_amdgcn_readlane(bra_key, leader);
+                const bool mine = valid && bra_key == key;
+                rem &= ~__ballot(mine);
+                const int ra = __builtin_amdgcn_readlane(oa, leader) + a, cb = __builtin_amdgcn_readlane(ob, leader);
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    const A v = wave_sum(mine ? f2 * jab[b] : A(0));
+                    if ((int)(threadIdx.x & 63) == leader) lds_add(&AJ[ra * N + cb + b], v);
+                }
+            }
         } else {
 #pragma unroll
             for (int b = 0; b < NB; b++) lds_add(&AJ[(oa + a) * N + ob + b], f2 * jab[b]);
         }
+        if (valid) {
 #pragma unroll
-        for (int c = 0; c < NC; c++) lds_add(&AK[(oa + a) * N + oc + c], f * kac[c]);
+            for (int c = 0; c < NC; c++) lds_add(&AK[(oa + a) * N + oc + c], f * kac[c]);
 #pragma unroll
-        for (int d = 0; d < ND; d++) lds_add(&AK[(oa + a) * N + od + d], f * kad[d]);
+            for (int d = 0; d < ND; d++) lds_add(&AK[(oa + a) * N + od + d], f * kad[d]);
+        }
     }
+    if (valid) {
 #pragma unroll
-    for (int c = 0; c < NC; c++)
+        for (int c = 0; c < NC; c++)
 #pragma unroll
-        for (int d = 0; d < ND; d++) lds_add(&AJ[(oc + c) * N + od + d], f2 * jcd[c][d]);
+            for (int d = 0; d < ND; d++) lds_add(&AJ[(oc + c) * N + od + d], f2 * jcd[c][d]);
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
+        for (int b = 0; b < NB; b++) {
 #pragma unroll
-        for (int c = 0; c < NC; c++) lds_add(&AK[(ob + b) * N + oc + c], f * kbc[b][c]);
+            for (int c = 0; c < NC; c++) lds_add(&AK[(ob + b) * N + oc + c], f * kbc[b][c]);
 #pragma unroll
-        for (int d = 0; d < ND; d++) lds_add(&AK[(ob + b) * N + od + d], f * kbd[b][d]);
+            for (int d = 0; d < ND; d++) lds_add(&AK[(ob + b) * N + od + d], f * kbd[b][d]);
+        }
     }
 }
 

@@ -78,9 +78,13 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
     // issues the next batch's loads before this batch's scatter: with one
     // work group per CU, one quartet in flight per lane leaves the HBM stream
     // latency-bound.  The integrals stay in the storage type until use.
-    constexpr int U = sizeof(S) == 4 ? (NCOMP <= 3 ? 4 : NCOMP <= 9 ? 2 : 1)
+    constexpr int U = sizeof(S) == 4 ? (NCOMP <= 3 ? 4 : 1)
                                      : (NCOMP == 1 ? 4 : NCOMP <= 3 ? 2 : 1);
     constexpr bool kAhead = NCOMP <= 27;
+    // segmented J_ab sums for the classes with at most three bra functions
+    // (the pp-bra classes keep the uniform-bra sum and per-lane adds, whose
+    // registers the segmented form would spill)
+    constexpr bool kFull = NA * NB <= 3;
     const long ustep = (long)U * step;
     const size_t qoff = md.q0[C];
     // (i, j) of the lane's quartet advanced by step in row-major order over
@@ -103,13 +107,16 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
             }
         }
     };
+    // kFull: the loop runs while the wavefront's first lane (its smallest q)
+    // has quartets left, so that all 64 lanes reach every scatter together
     long q = lo + threadIdx.x;
-    if (q >= hi) return;
+    const long lane0 = kFull ? (long)(threadIdx.x & 63) : 0;
+    if (q - lane0 >= hi) return;
     int ci, cj;
     decode_quartet_jk(C, q, nket, ci, cj);
     S cur[U][NCOMP];
     if constexpr (kAhead) load(q, cur);
-    for (; q < hi; q += ustep) {
+    for (; q - lane0 < hi; q += ustep) {
         S I[U][NCOMP];
         if constexpr (kAhead) {
 #pragma unroll
@@ -127,21 +134,29 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
         for (int u = 0; u < U; u++) {
             bi[u] = ci;
             bj[u] = cj;
+            P1[u] = P2[u] = make_int2(0, 0);
             if (q + (long)u * step < hi) {
                 P1[u] = pb[ci];
                 P2[u] = pk[cj];
             }
             advance(ci, cj);
         }
+        // kFull: every lane of the wavefront scatters (lanes past the range
+        // with zero integrals), so that J_ab is summed per bra pair across it
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (q + (long)u * step < hi) {
+            const bool ok = q + (long)u * step < hi;
+            if (kFull || ok) {
+                if (!ok) {
+#pragma unroll
+                    for (int k = 0; k < NCOMP; k++) I[u][k] = S(0);
+                }
                 A f = A(1);
                 if (P1[u].x >> 16) f *= A(0.5);
                 if (P2[u].x >> 16) f *= A(0.5);
                 if (class_tri(C) && bi[u] == bj[u]) f *= A(0.5);
-                jk_scatter<NA, NB, NC, ND, A, S>(I[u], P1[u].x & 0xffff, P1[u].y, P2[u].x & 0xffff, P2[u].y, f, bi[u],
-                                                 ld, Ps, AJ, AK);
+                jk_scatter<NA, NB, NC, ND, A, S, kFull>(I[u], P1[u].x & 0xffff, P1[u].y, P2[u].x & 0xffff, P2[u].y,
+                                                        f, ok ? bi[u] : -1, ld, Ps, AJ, AK, ok);
             }
         }
     }
