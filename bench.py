@@ -40,8 +40,8 @@ COUNTERS = os.path.join(ROOT, "profiles", "counters_4096mol_9-11heavy_mixed.json
 CSRC = os.path.join(ROOT, "paper_2311_01135_amd", "csrc")
 # kernel family -> (rocprofv3 kernel-name prefix, sources its code comes from)
 COUNTER_KERNELS = {
-    "xc": ("ks::xc_kernel<", ["k_xc.hip"]),
-    "jk": ("ks::jk_class_kernel<", ["k_jk.hip", "jk_scatter.h"]),
+    "xc": ("ks::xc_kernel<", ["k_xc.hip", "wave.h"]),
+    "jk": ("ks::jk_class_kernel<", ["k_jk.hip", "jk_scatter.h", "wave.h"]),
     "eri": ("ks::eri_class_kernel<", ["k_ints.hip"]),
 }
 
