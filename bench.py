@@ -68,6 +68,8 @@ def parse():
     p.add_argument("--coarse-grid", type=str, default="25,8,16",
                    help="radial,theta,phi of the coarse start grid (0,0,0 = none); results stay the main grid's")
     p.add_argument("--direct", action="store_true", help="integral-direct J/K (ERIs recomputed every iteration)")
+    p.add_argument("--no-direct-leg", action="store_true",
+                   help="skip the 64 x 20-30-heavy-atom integral-direct leg of the config legs")
     p.add_argument("--schwarz-tol", type=float, default=0.0, help="Schwarz screening threshold (0 = off)")
     p.add_argument("--basis", choices=["sto-3g", "6-31g"], default="sto-3g",
                    help="6-31G covers H, C, N, O: molecules with F are replaced by F-free trees of the same size")
@@ -414,11 +416,14 @@ def serving_leg(ks, args, reqs):
                 mean_iterations=float(iters[np.isfinite(lat)].mean()))
 
 
-def config_legs(ks, torch, water, c1, args):
-    """The small workloads: one water molecule (FP64, seed 0) solved alone,
+def config_legs(ks, torch, water, c1, big, args):
+    """The other workloads: one water molecule (FP64, seed 0) solved alone,
     its time per solve and |dE|, |d gap| against the stored oracle result; a
     batch of 256 nine-heavy-atom molecules (FP64, seed 1) with its solves/s
-    and ERI rates.  Main grid only (no coarse start), default options."""
+    and ERI rates (main grid only, no coarse start, default options); and,
+    when given, 64 molecules of 20-30 heavy atoms (seed 4) solved
+    integral-direct in mixed precision with Schwarz screening at 1e-10 on the
+    75 x 18 x 36 grid (with the 25 x 8 x 16 coarse start), one timed solve."""
     out = {}
     gold = os.path.join(ROOT, "tests", "golden", "oracle_scf_samples.json")
     with ks.Batch(water) as b:             # warm-up
@@ -464,6 +469,32 @@ def config_legs(ks, torch, water, c1, args):
     print("configs: water %.1f ms/solve |dE| %.1e; 256x9 FP64 %.1f solves/s"
           % (w["s_per_solve_median"] * 1e3, w.get("abs_dE_vs_oracle", float("nan")),
              out["fp64_256x9"]["solves_per_s"]), file=sys.stderr, flush=True)
+    if big:
+        kw = dict(prec=ks.KS_MIXED, direct=1, schwarz_tol=1e-10, n_rad=75, n_theta=18, n_phi=36,
+                  coarse_rad=25, coarse_theta=8, coarse_phi=16)
+        kw.update(autotune.tuned_options(ks.KS_MIXED, [molgen.nbf_sto3g(z) for z, _ in big]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with ks.Batch(big, **kw) as b:
+            b.set_timing(True)
+            b.scf_solve()
+            res = b.results(density=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            kt = b.kernel_times()
+            nbf = list(b.nbf)
+            ngrid = float(sum(b.n_grid))
+        ms = {k: round(v[0], 3) for k, v in kt.items() if k in ("jk_direct", "xc", "eigh", "diis", "grid", "lowdin")}
+        out["direct_64x20-30"] = dict(
+            workload="64 molecules, 20-30 heavy atoms, seed 4, B3LYP/STO-3G, mixed precision, integral-direct J/K "
+                     "with Schwarz screening 1e-10, grid 75x18x36 per atom, SCF started on a 25x8x16 coarse grid; "
+                     "one timed solve",
+            solves_per_s=len(big) / wall, s_per_batch=wall, nbf_min=min(nbf), nbf_max=max(nbf), grid_points=ngrid,
+            iterations_mean=float(np.mean([x["n_iter"] for x in res])), iterations_max=int(max(x["n_iter"] for x in res)),
+            coarse_grid_mean=float(np.mean([x["n_coarse"] for x in res])),
+            unconverged=int(sum(x["status"] != 1 for x in res)), kernel_ms_avg=ms)
+        print("configs: 64x20-30 direct %.2f solves/s (%.1f s per batch, %.1f iterations)"
+              % (len(big) / wall, wall, out["direct_64x20-30"]["iterations_mean"]), file=sys.stderr, flush=True)
     return out
 
 
@@ -541,8 +572,9 @@ def main():
     legs = not args.no_configs and args.basis == "sto-3g"
     water = [molgen.water(0)] if legs else []
     c1 = gen_batch(256, 1, 9) if legs else []
-    print("generated %d + %d + %d molecules in %.1f s" % (len(mols), len(reqs), len(c1), time.perf_counter() - t_gen),
-          file=sys.stderr, flush=True)
+    big = gen_batch(64, 4, (20, 30)) if legs and not args.no_direct_leg else []
+    print("generated %d + %d + %d + %d molecules in %.1f s" % (len(mols), len(reqs), len(c1), len(big),
+                                                               time.perf_counter() - t_gen), file=sys.stderr, flush=True)
 
     import torch
     from paper_2311_01135_amd import ks
@@ -659,7 +691,7 @@ def main():
 
     legs_out = None
     if legs:
-        legs_out = config_legs(ks, torch, water, c1, args)
+        legs_out = config_legs(ks, torch, water, c1, big, args)
 
     serving = None
     if args.serve_requests > 0:

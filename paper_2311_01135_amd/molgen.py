@@ -98,18 +98,29 @@ def water(seed: int = 0):
     return np.array([8, 1, 1], dtype=np.int32), xyz
 
 
+def _norm(v):
+    """|v| as np.linalg.norm forms it for a vector (sqrt of v . v)."""
+    return math.sqrt(v.dot(v))
+
+
 def _unit(v):
-    return v / np.linalg.norm(v)
+    return v / _norm(v)
+
+
+def _cross(a, b):
+    """a x b of two 3-vectors (the same products and differences as np.cross,
+    without its per-call array handling, which dominated the generator)."""
+    return np.array([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]])
 
 
 def _perp(u):
     a = np.array([1.0, 0.0, 0.0]) if abs(u[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
-    return _unit(np.cross(u, a))
+    return _unit(_cross(u, a))
 
 
 def _rotate(v, axis, ang):
     axis = _unit(axis)
-    return (v * math.cos(ang) + np.cross(axis, v) * math.sin(ang)
+    return (v * math.cos(ang) + _cross(axis, v) * math.sin(ang)
             + axis * np.dot(axis, v) * (1 - math.cos(ang)))
 
 
@@ -139,14 +150,14 @@ def _new_direction(rng, dirs):
     if k == 2:
         u1, u2 = dirs
         b = u1 + u2
-        b = -_unit(b) if np.linalg.norm(b) > 1e-8 else _perp(u1)
-        nrm = np.cross(u1, u2)
-        nrm = _unit(nrm) if np.linalg.norm(nrm) > 1e-8 else _perp(b)
+        b = -_unit(b) if _norm(b) > 1e-8 else _perp(u1)
+        nrm = _cross(u1, u2)
+        nrm = _unit(nrm) if _norm(nrm) > 1e-8 else _perp(b)
         half = _TET / 2
         sgn = 1.0 if rng.uniform() < 0.5 else -1.0
         return _tilt(rng, _unit(b * math.cos(half) + sgn * nrm * math.sin(half)))
     s = sum(dirs)
-    d = -_unit(s) if np.linalg.norm(s) > 1e-8 else _perp(dirs[0])
+    d = -_unit(s) if _norm(s) > 1e-8 else _perp(dirs[0])
     return _tilt(rng, d)
 
 
@@ -224,7 +235,7 @@ def _place(rng, pos, dirs, p, length, max_local=100):
     for _ in range(max_local):
         d = _new_direction(rng, dirs[p])
         x = pos[p] + length * d
-        if all(np.linalg.norm(x - q) >= 0.9 for q in pos):
+        if all(_norm(x - q) >= 0.9 for q in pos):
             return d, x
     return None
 
@@ -313,7 +324,7 @@ def bonds(Z, xyz):
             if Z[i] == 1 and Z[j] == 1:
                 continue
             cut = 1.7 if (Z[i] > 1 and Z[j] > 1) else 1.25
-            if np.linalg.norm(xyz[i] - xyz[j]) < cut:
+            if _norm(xyz[i] - xyz[j]) < cut:
                 out.append((j, i))
     return out
 
