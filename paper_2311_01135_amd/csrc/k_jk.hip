@@ -73,11 +73,12 @@ __device__ __forceinline__ void digest_class(const JkArgs& g, const MolDesc& md,
     const int2* __restrict__ pk = g.pao[class_ket(C)] + md.pair0[class_ket(C)];
     const int nket = md.npair[class_ket(C)];
     const int step = blockDim.x;
-    // Each lane takes U of its quartets (q, q + step, ...) per batch and
-    // loads their integrals together, and (classes of up to 27 components)
-    // issues the next batch's loads before this batch's scatter: with one
-    // work group per CU, one quartet in flight per lane leaves the HBM stream
-    // latency-bound.  The integrals stay in the storage type until use.
+    // Each lane takes U of its quartets (q, q + step, ...) per batch: their
+    // integrals and pair-table entries are loaded before the first scatter
+    // (a pair-table load per quartet in front of its scatter left its
+    // latency exposed), and in classes of up to 27 components the next
+    // batch's integrals are loaded before this batch's scatter.  The
+    // integrals stay in the storage type until use.
     constexpr int U = sizeof(S) == 4 ? (NCOMP <= 3 ? 4 : 1)
                                      : (NCOMP == 1 ? 4 : NCOMP <= 3 ? 2 : 1);
     constexpr bool kAhead = NCOMP <= 27;
