@@ -73,7 +73,7 @@ def test_bench_batch_vs_oracle_samples(ks, bench_refs, bench_mols, prec):
             if prec == 0:
                 assert abs(r["n_iter"] - g["n_iter"]) <= 1
         if prec == 0:
-            # full-size densities (the benchmark spec: FP64 max|dP| <= 1e-6)
+            # full-size densities (FP64: max|dP| <= 1e-6)
             dens = np.load(os.path.join(GOLDEN, "oracle_density_seed2.npz"))
             for m in range(3):
                 dP = np.abs(b.result(m)["P"] - dens["P_default_%d" % m]).max()
